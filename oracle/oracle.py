@@ -1,0 +1,191 @@
+"""ctypes front end of the CPU oracle (``sro_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark.  The product library never imports it.
+
+Every function takes and returns numpy arrays.  ``build()`` compiles the C
+source with ``-O2 -ffp-contract=off`` (no fused multiply-add, no fast-math), so
+all binary64 results are fixed to the bit.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sro_oracle.c")
+_LIB = os.path.join(_HERE, "libsro_oracle.so")
+
+FCC, BCC = 0, 1
+MODE_DISJOINT, MODE_BEST = 0, 1
+
+
+class McStats(ctypes.Structure):
+    _fields_ = [
+        ("trials", ctypes.c_int64),
+        ("null_trials", ctypes.c_int64),
+        ("commits", ctypes.c_int64),
+        ("steps", ctypes.c_int64),
+        ("stop_reason", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("S", ctypes.c_double),
+        ("F", ctypes.c_double),
+        ("log_len", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
+def build() -> str:
+    """Compile the oracle into a shared library next to its source."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-Wall",
+           "-shared", "-fPIC", _SRC, "-o", _LIB + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32, i64 = ctypes.c_int, ctypes.c_int64
+        L.or_shells.argtypes = [i32, i32, P, P, P]
+        L.or_shells.restype = i32
+        L.or_n_sites.argtypes = [i32, P]
+        L.or_n_sites.restype = i64
+        L.or_site_pos.argtypes = [i32, P, i64, P]
+        L.or_site_id.argtypes = [i32, P, P]
+        L.or_site_id.restype = i64
+        L.or_neighbors.argtypes = [i32, P, i32, i64, P]
+        L.or_neighbors.restype = i32
+        L.or_validate.argtypes = [i32, P, i32, i32, P]
+        L.or_validate.restype = i32
+        L.or_counts.argtypes = [i32, P, i32, i32, P, P]
+        L.or_alpha_objective.argtypes = [i32, P, i32, i32, P, P, P, P, P, P, P]
+        L.or_swap_delta.argtypes = [i32, P, i32, i32, P, i64, i64, P]
+        L.or_swap_dS.argtypes = [i32, P, i32, i32, P, i64, i64, P, P]
+        L.or_swap_dS.restype = ctypes.c_double
+        L.or_philox4x32_10.argtypes = [P, P, P]
+        L.or_mc_run.argtypes = [i32, P, i32, i32, P, P, ctypes.c_uint64, ctypes.c_uint32, i64,
+                                i32, i32, i32, ctypes.c_double, P, P, i64,
+                                ctypes.POINTER(McStats), P]
+        L.or_mc_run.restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _L(L) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(L, dtype=np.int32).reshape(3))
+
+
+def shells(lattice: int, n_shells: int):
+    """(r2[S], z[S], offsets[sum z][3]) in half-lattice units."""
+    r2 = np.zeros(4, np.int32)
+    z = np.zeros(4, np.int32)
+    off = np.zeros((64, 3), np.int32)
+    n = lib().or_shells(lattice, n_shells, _p(r2), _p(z), _p(off))
+    if n < 0:
+        raise ValueError("bad lattice or shell count")
+    return r2[:n_shells].copy(), z[:n_shells].copy(), off[:n].copy()
+
+
+def n_sites(lattice: int, L) -> int:
+    return int(lib().or_n_sites(lattice, _p(_L(L))))
+
+
+def site_pos(lattice: int, L, p: int) -> np.ndarray:
+    pos = np.zeros(3, np.int32)
+    lib().or_site_pos(lattice, _p(_L(L)), p, _p(pos))
+    return pos
+
+
+def neighbors(lattice: int, L, n_shells: int, p: int) -> np.ndarray:
+    out = np.zeros(64, np.int64)
+    n = lib().or_neighbors(lattice, _p(_L(L)), n_shells, p, _p(out))
+    return out[:n].copy()
+
+
+def validate(lattice: int, L, M: int, S: int, species: np.ndarray | None) -> int:
+    sp = None if species is None else np.ascontiguousarray(species, dtype=np.int8)
+    return int(lib().or_validate(lattice, _p(_L(L)), M, S, None if sp is None else _p(sp)))
+
+
+def counts(lattice: int, L, M: int, S: int, species: np.ndarray) -> np.ndarray:
+    sp = np.ascontiguousarray(species, dtype=np.int8)
+    out = np.zeros((S, M, M), np.int64)
+    lib().or_counts(lattice, _p(_L(L)), M, S, _p(sp), _p(out))
+    return out
+
+
+def alpha_objective(lattice: int, L, M: int, S: int, species: np.ndarray, cnt: np.ndarray,
+                    target: np.ndarray, weight: np.ndarray):
+    """(alpha[S][M][M], term[S][M][M], S, F) by Eq. 2-3 from exact counts."""
+    sp = np.ascontiguousarray(species, dtype=np.int8)
+    c = np.ascontiguousarray(cnt, dtype=np.int64)
+    t = np.ascontiguousarray(target, dtype=np.float64).reshape(S, M, M)
+    w = np.ascontiguousarray(weight, dtype=np.float64).reshape(S)
+    alpha = np.zeros((S, M, M))
+    term = np.zeros((S, M, M))
+    sf = np.zeros(2)
+    lib().or_alpha_objective(lattice, _p(_L(L)), M, S, _p(sp), _p(c), _p(t), _p(w), _p(alpha),
+                             _p(term), _p(sf))
+    return alpha, term, float(sf[0]), float(sf[1])
+
+
+def swap_delta(lattice: int, L, M: int, S: int, species: np.ndarray, p: int, q: int):
+    sp = np.ascontiguousarray(species, dtype=np.int8)
+    out = np.zeros((S, M, M), np.int64)
+    lib().or_swap_delta(lattice, _p(_L(L)), M, S, _p(sp), p, q, _p(out))
+    return out
+
+
+def swap_dS(lattice: int, L, M: int, S: int, species: np.ndarray, p: int, q: int,
+            target: np.ndarray, weight: np.ndarray) -> float:
+    sp = np.ascontiguousarray(species, dtype=np.int8)
+    t = np.ascontiguousarray(target, dtype=np.float64).reshape(S, M, M)
+    w = np.ascontiguousarray(weight, dtype=np.float64).reshape(S)
+    return float(lib().or_swap_dS(lattice, _p(_L(L)), M, S, _p(sp), p, q, _p(t), _p(w)))
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(4))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(2))
+    out = np.zeros(4, np.uint32)
+    lib().or_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def mc_run(lattice: int, L, M: int, S: int, target, weight, species: np.ndarray, *, seed: int,
+           chain_id: int, n_trials: int, B: int = 64, mode: int = MODE_DISJOINT,
+           depth_limit: int = 0, tau: float = 0.0, log_cap: int | None = None):
+    """Run one chain.  Returns (final species, log[n][4] uint32, stats dict,
+    maintained counts[S][M][M])."""
+    sp = np.array(species, dtype=np.int8, copy=True)
+    t = np.ascontiguousarray(target, dtype=np.float64).reshape(S, M, M)
+    w = np.ascontiguousarray(weight, dtype=np.float64).reshape(S)
+    if log_cap is None:
+        log_cap = n_trials
+    log = np.zeros((max(log_cap, 1), 4), np.uint32)
+    st = McStats()
+    cnt = np.zeros((S, M, M), np.int64)
+    rc = lib().or_mc_run(lattice, _p(_L(L)), M, S, _p(t), _p(w), seed, chain_id, n_trials, B,
+                         mode, depth_limit, tau, _p(sp), _p(log), log_cap, ctypes.byref(st),
+                         _p(cnt))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the problem (code {rc})")
+    return sp, log[: st.log_len].copy(), st.as_dict(), cnt
