@@ -134,17 +134,17 @@ def counts(lattice: int, L, M: int, S: int, species: np.ndarray) -> np.ndarray:
 
 def alpha_objective(lattice: int, L, M: int, S: int, species: np.ndarray, cnt: np.ndarray,
                     target: np.ndarray, weight: np.ndarray):
-    """(alpha[S][M][M], term[S][M][M], S, F) by Eq. 2-3 from exact counts."""
+    """(alpha[S][M][M], sq[S][M][M] = (alpha - target)^2, S, F) by Eq. 2-3."""
     sp = np.ascontiguousarray(species, dtype=np.int8)
     c = np.ascontiguousarray(cnt, dtype=np.int64)
     t = np.ascontiguousarray(target, dtype=np.float64).reshape(S, M, M)
     w = np.ascontiguousarray(weight, dtype=np.float64).reshape(S)
     alpha = np.zeros((S, M, M))
-    term = np.zeros((S, M, M))
+    sq = np.zeros((S, M, M))
     sf = np.zeros(2)
     lib().or_alpha_objective(lattice, _p(_L(L)), M, S, _p(sp), _p(c), _p(t), _p(w), _p(alpha),
-                             _p(term), _p(sf))
-    return alpha, term, float(sf[0]), float(sf[1])
+                             _p(sq), _p(sf))
+    return alpha, sq, float(sf[0]), float(sf[1])
 
 
 def swap_delta(lattice: int, L, M: int, S: int, species: np.ndarray, p: int, q: int):

@@ -222,8 +222,9 @@ void or_species_counts(int64_t N, int M, const int8_t *species, int64_t *n_out) 
  * Eq. 2 and Eq. 3 in binary64.  With P_ij = N_ij / (n_i z_k) and c_j = n_j / N,
  * alpha_ij = 1 - P_ij / c_j = 1 - N_ij * N / (n_i n_j z_k).  The factor
  * R = N / (n_i n_j z_k) is one IEEE division of two exact integers; then
- * alpha = 1 - N_ij * R, d = alpha - target, term = w_k * (d * d), and
- * S = sum of terms in (k, i, j) row-major order from +0.0, F = sqrt(S).
+ * alpha = 1 - N_ij * R and d = alpha - target.  Eq. 3 is evaluated with its own
+ * nesting: Q_k = sum over (i, j) row-major of d * d (from +0.0), then
+ * S = sum over k of w_k * Q_k (from +0.0), F = sqrt(S).
  */
 void or_ratio_table(int64_t N, int M, int S, const int *z, const int64_t *n, double *R) {
     for (int k = 0; k < S; ++k)
@@ -234,16 +235,17 @@ void or_ratio_table(int64_t N, int M, int S, const int *z, const int64_t *n, dou
             }
 }
 
-static double term_of(int64_t count, double R, double t, double w) {
+/* squared deviation (alpha - target)^2 of one entry with pair count `count` */
+static double sq_dev(int64_t count, double R, double t) {
     double alpha = 1.0 - (double)count * R;
     double d = alpha - t;
-    return w * (d * d);
+    return d * d;
 }
 
-/* alpha[S][M][M], term[S][M][M], and S_F[2] = {S, F} from exact counts */
+/* alpha[S][M][M], sq[S][M][M] = (alpha - target)^2, and S_F[2] = {S, F} */
 void or_alpha_objective(int lattice, const int *L, int M, int S, const int8_t *species,
                         const int64_t *counts, const double *target, const double *weight,
-                        double *alpha, double *term, double *S_F) {
+                        double *alpha, double *sq, double *S_F) {
     int r2[OR_MAX_SHELLS], z[OR_MAX_SHELLS], off[OR_MAX_OFFSETS * 3];
     or_shells(lattice, S, r2, z, off);
     int64_t N = or_n_sites(lattice, L);
@@ -252,17 +254,19 @@ void or_alpha_objective(int lattice, const int *L, int M, int S, const int8_t *s
     double R[OR_MAX_SHELLS * OR_MAX_SPECIES * OR_MAX_SPECIES];
     or_ratio_table(N, M, S, z, n, R);
     double sum = 0.0;
-    for (int k = 0; k < S; ++k)
+    for (int k = 0; k < S; ++k) {
+        double Q = 0.0;
         for (int i = 0; i < M; ++i)
             for (int j = 0; j < M; ++j) {
                 int e = (k * M + i) * M + j;
                 double a = 1.0 - (double)counts[e] * R[e];
                 double d = a - target[e];
-                double tm = weight[k] * (d * d);
                 if (alpha) alpha[e] = a;
-                if (term) term[e] = tm;
-                sum = sum + tm;
+                if (sq) sq[e] = d * d;
+                Q = Q + d * d;
             }
+        sum = sum + weight[k] * Q;
+    }
     S_F[0] = sum;
     S_F[1] = sqrt(sum);
 }
@@ -309,19 +313,23 @@ void or_swap_delta(int lattice, const int *L, int M, int S, const int8_t *specie
     }
 }
 
-/* dS = sum over (k, i, j) row-major of term(N + dN) - term(N), from +0.0.
- * Entries with dN = 0 add exactly +0.0. */
+/* dS = sum over k of w_k * dQ_k (from +0.0), where dQ_k is the sum over (i, j)
+ * row-major of sq(N + dN) - sq(N) (from +0.0).  Entries with dN = 0 add
+ * exactly +0.0. */
 static double delta_objective(int M, int S, const int64_t *counts, const int64_t *dN,
                               const double *R, const double *target, const double *weight,
-                              const double *term) {
+                              const double *sq) {
     double acc = 0.0;
-    for (int k = 0; k < S; ++k)
+    for (int k = 0; k < S; ++k) {
+        double dQ = 0.0;
         for (int i = 0; i < M; ++i)
             for (int j = 0; j < M; ++j) {
                 int e = (k * M + i) * M + j;
-                double tn = term_of(counts[e] + dN[e], R[e], target[e], weight[k]);
-                acc = acc + (tn - term[e]);
+                double sn = sq_dev(counts[e] + dN[e], R[e], target[e]);
+                dQ = dQ + (sn - sq[e]);
             }
+        acc = acc + weight[k] * dQ;
+    }
     return acc;
 }
 
@@ -336,14 +344,14 @@ double or_swap_dS(int lattice, const int *L, int M, int S, const int8_t *species
     int64_t *counts = malloc(sizeof(int64_t) * S * M * M);
     int64_t *dN = malloc(sizeof(int64_t) * S * M * M);
     double R[OR_MAX_SHELLS * OR_MAX_SPECIES * OR_MAX_SPECIES];
-    double term[OR_MAX_SHELLS * OR_MAX_SPECIES * OR_MAX_SPECIES];
+    double sq[OR_MAX_SHELLS * OR_MAX_SPECIES * OR_MAX_SPECIES];
     or_ratio_table(N, M, S, z, n, R);
     or_counts(lattice, L, M, S, species, counts);
     for (int k = 0; k < S; ++k)
         for (int e = k * M * M; e < (k + 1) * M * M; ++e)
-            term[e] = term_of(counts[e], R[e], target[e], weight[k]);
+            sq[e] = sq_dev(counts[e], R[e], target[e]);
     or_swap_delta(lattice, L, M, S, species, p, q, dN);
-    double r = delta_objective(M, S, counts, dN, R, target, weight, term);
+    double r = delta_objective(M, S, counts, dN, R, target, weight, sq);
     free(counts);
     free(dN);
     return r;
@@ -443,7 +451,7 @@ int or_mc_run(int lattice, const int *L, int M, int S, const double *target,
     or_species_counts(N, M, species, n);
     const int E = S * M * M;
     double R[OR_MAX_SHELLS * OR_MAX_SPECIES * OR_MAX_SPECIES];
-    double term[OR_MAX_SHELLS * OR_MAX_SPECIES * OR_MAX_SPECIES];
+    double sq[OR_MAX_SHELLS * OR_MAX_SPECIES * OR_MAX_SPECIES];
     or_ratio_table(N, M, S, z, n, R);
     int64_t *counts = malloc(sizeof(int64_t) * E);
     int64_t *dN_all = malloc(sizeof(int64_t) * E * (size_t)B);
@@ -453,7 +461,7 @@ int or_mc_run(int lattice, const int *L, int M, int S, const double *target,
     or_counts(lattice, L, M, S, species, counts);
     for (int k = 0; k < S; ++k)
         for (int e = k * M * M; e < (k + 1) * M * M; ++e)
-            term[e] = term_of(counts[e], R[e], target[e], weight[k]);
+            sq[e] = sq_dev(counts[e], R[e], target[e]);
 
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     memset(stats, 0, sizeof(*stats));
@@ -481,7 +489,7 @@ int or_mc_run(int lattice, const int *L, int M, int S, const double *target,
             }
             int64_t *dN = dN_all + (size_t)slot * E;
             or_swap_delta(lattice, L, M, S, species, t->p, t->q, dN);
-            t->dS = delta_objective(M, S, counts, dN, R, target, weight, term);
+            t->dS = delta_objective(M, S, counts, dN, R, target, weight, sq);
             if (t->dS < -tau) {
                 t->improving = 1;
                 order[n_impr++] = slot;
@@ -512,16 +520,16 @@ int or_mc_run(int lattice, const int *L, int M, int S, const double *target,
             if (conflict) continue;
             double dS = t->dS;
             if (n_commit > 0) {
-                dS = delta_objective(M, S, counts, dN, R, target, weight, term);
+                dS = delta_objective(M, S, counts, dN, R, target, weight, sq);
                 if (!(dS < -tau)) continue;
             }
-            /* commit: swap species, update counts and the cached terms */
+            /* commit: swap species, update counts and the cached squared deviations */
             species[t->p] = (int8_t)t->b;
             species[t->q] = (int8_t)t->a;
             for (int e = 0; e < E; ++e) counts[e] += dN[e];
             for (int k = 0; k < S; ++k)
                 for (int e = k * M * M; e < (k + 1) * M * M; ++e)
-                    term[e] = term_of(counts[e], R[e], target[e], weight[k]);
+                    sq[e] = sq_dev(counts[e], R[e], target[e]);
             if (log && stats->commits < log_cap) {
                 uint32_t *rec = log + 4 * stats->commits;
                 rec[0] = (uint32_t)step;

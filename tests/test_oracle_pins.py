@@ -149,7 +149,7 @@ def test_alpha_row_constraint_and_zero_objective():
         c = orc.counts(lattice, L, M, S, sp)
         cj = np.bincount(sp, minlength=M) / N
         w = rng.uniform(0.1, 1.0, S)
-        alpha, term, S_, F = orc.alpha_objective(lattice, L, M, S, sp, c, np.zeros((S, M, M)), w)
+        alpha, sq, S_, F = orc.alpha_objective(lattice, L, M, S, sp, c, np.zeros((S, M, M)), w)
         assert np.all(np.abs(alpha @ cj) < 8 * M * 2.0**-52)
         np.testing.assert_array_equal(alpha, np.transpose(alpha, (0, 2, 1)))
         assert S_ == pytest.approx(bf.objective(c, sp, np.zeros((S, M, M)), w, bf.Z[lattice]),
