@@ -1,0 +1,242 @@
+/*
+ * pyhea.h - C ABI of the MI355X (gfx950) library for Warren-Cowley
+ * short-range-order (SRO) evaluation and SRO-targeted Monte Carlo structure
+ * search, after Niu & Liu, "Short-Range Order Based Ultra Fast Large-Scale
+ * Modeling of High-Entropy Alloys" (arXiv:2411.18906).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns a pyhea_status (0 = OK, negative = error) and never
+ *    throws.  After an error, pyhea_last_error() returns a message for the
+ *    calling thread.
+ *  - "_dev" pointers are device (HBM) pointers on the current HIP device, e.g.
+ *    torch tensor data_ptr(); "_host" pointers are ordinary host memory.  The
+ *    caller owns every buffer it passes; the library keeps no pointer after a
+ *    call returns, except the serving API, which copies its inputs.
+ *  - `stream` is a hipStream_t (NULL = the default stream); work is ordered on
+ *    it.  Calls that return results in host memory synchronise that stream.
+ *  - Geometry: a supercell of L[0] x L[1] x L[2] conventional cubic cells of an
+ *    FCC (4 sites per cell) or BCC (2 sites per cell) lattice, S = A L^3 sites
+ *    (Sec. 2.2, Table 1 caption).  Positions are in half lattice constants:
+ *    FCC sites 2c + {(0,0,0),(1,1,0),(1,0,1),(0,1,1)}, BCC 2c + {(0,0,0),(1,1,1)}.
+ *    Site id p = ((cz*L[1] + cy)*L[0] + cx)*A + b.  Boundaries are periodic.
+ *  - Coordination shell k (k = 1..4) is the set of lattice vectors of the k-th
+ *    smallest length: FCC z = 12, 6, 24, 12; BCC z = 8, 6, 12, 24.  Pairs are
+ *    counted once per (site, offset), so on cells two cells wide a neighbour
+ *    reachable along two offsets counts twice.
+ *  - Configurations are int8 species ids in [0, M), one byte per site.
+ *  - Pair counts N[k][i][j] = #{(p, d): d in shell k, s_p = i, s_{p+d} = j}
+ *    (ordered and symmetric).  alpha and the objective follow Eq. 2-3 in IEEE
+ *    binary64 with no fused multiply-add:
+ *        R     = (double)N_sites / (double)(n_i * n_j * z_k)
+ *        alpha = 1 - N[k][i][j] * R           (P_ij = N_ij/(n_i z_k), c_j = n_j/N)
+ *        Q_k   = sum_{i,j row-major} (alpha - target)^2,   S = sum_k w_k Q_k,
+ *        F     = sqrt(S)                      (Eq. 3: F is the fitness)
+ *  - Limits: M in [2, 8]; S in [1, 4]; N_sites * max z_k < 2^31; no shell
+ *    offset may map a site onto itself (PYHEA_EINVAL otherwise).
+ */
+#ifndef PYHEA_H
+#define PYHEA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pyhea_status;
+#define PYHEA_OK 0
+#define PYHEA_EINVAL (-1)     /* malformed descriptor or input data            */
+#define PYHEA_ENOMEM (-2)     /* device allocation failed / over HBM budget    */
+#define PYHEA_EDEVICE (-3)    /* a HIP runtime call failed                     */
+#define PYHEA_EBUSY (-4)      /* serving: job not finished yet                 */
+#define PYHEA_ECANCELLED (-5) /* serving: job cancelled                        */
+#define PYHEA_ENOSYS (-6)     /* not supported in this build                   */
+#define PYHEA_ENOENT (-7)     /* serving: unknown job id                       */
+
+#define PYHEA_FCC 0
+#define PYHEA_BCC 1
+
+#define PYHEA_MODE_DISJOINT 0 /* commit every non-conflicting improving swap   */
+#define PYHEA_MODE_BEST 1     /* commit only the best swap of a step (Eq. 6)   */
+
+#define PYHEA_STOP_TRIALS 0 /* the trial budget was used up                    */
+#define PYHEA_STOP_DEPTH 1  /* depth_limit steps in a row committed nothing    */
+
+/* Problem geometry (Sec. 2.2: lattice type and supercell; Sec. 4.3: shells). */
+typedef struct {
+    int32_t lattice;   /* PYHEA_FCC or PYHEA_BCC                              */
+    int32_t L[3];      /* conventional cells along x, y, z (each >= 1)        */
+    int32_t n_species; /* M, 2..8                                             */
+    int32_t n_shells;  /* S, 1..4                                             */
+} pyhea_lattice;
+
+/* Objective of Eq. 3 (Sec. 4.4): user-specified target alphas and weights. */
+typedef struct {
+    const double *target; /* host, [S][M][M] row-major                        */
+    const double *weight; /* host, [S], each finite and >= 0                  */
+} pyhea_objective;
+
+/* Monte Carlo local search parameters (Sec. 4.2, Algorithm 3; Sec. 4.6). */
+typedef struct {
+    uint64_t seed;         /* Philox4x32-10 key = (lo32(seed), hi32(seed))         */
+    uint32_t chain_id;     /* Philox counter word 2; independent streams per chain */
+    int32_t cand_per_step; /* B, trial swaps evaluated per step ("tasks"), 1..256  */
+    int64_t n_trials;      /* T, total trial swaps (the last step may be partial)  */
+    int32_t commit_mode;   /* PYHEA_MODE_DISJOINT or PYHEA_MODE_BEST               */
+    int32_t depth_limit;   /* stop after this many steps without a commit; 0 = off */
+    double accept_tol;     /* tau: a swap is improving iff dS < -tau (tau >= 0)    */
+} pyhea_mc_params;
+
+/* Per-chain results. */
+typedef struct {
+    int64_t trials;      /* trial swaps drawn                                  */
+    int64_t null_trials; /* draws with equal species at both sites            */
+    int64_t commits;     /* swaps applied                                      */
+    int64_t steps;       /* steps run                                          */
+    int32_t stop_reason; /* PYHEA_STOP_*                                       */
+    int32_t status;      /* PYHEA_OK, or the chain's own error                 */
+    double S;            /* objective of the final configuration               */
+    double F;            /* sqrt(S), Eq. 3                                      */
+    int64_t log_len;     /* accepted-swap records written (min(commits, cap))  */
+} pyhea_mc_stats;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t pyhea_version(void);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *pyhea_last_error(void);
+
+/*
+ * Full SRO evaluation of one configuration (Sec. 4.3, Eq. 2; Sec. 4.4, Eq. 3).
+ *   species_dev  [N] int8, device.
+ *   obj          may be NULL: then alpha is still computed, S_F_host untouched.
+ *   counts_host  [S][M][M] int64 (may be NULL).
+ *   alpha_host   [S][M][M] double (may be NULL).
+ *   S_F_host     [2] = {S, F} (ignored when obj is NULL).
+ * Synchronous.  PYHEA_EINVAL if a species id is outside [0, M) or some
+ * species is absent (c_j = 0 leaves Eq. 2 undefined).
+ */
+pyhea_status pyhea_sro_eval(const pyhea_lattice *lat, const int8_t *species_dev,
+                            const pyhea_objective *obj, int64_t *counts_host, double *alpha_host,
+                            double *S_F_host, void *stream);
+
+/*
+ * Full SRO evaluation of K configurations of one geometry in one launch
+ * (the fitness evaluation of a solution pool, Algorithm 1).
+ *   species_dev  [K][N] int8, device.
+ *   counts_dev   [K][S][M][M] int32, device, overwritten.
+ *   obj, S_F_dev optional (both or neither): S_F_dev [K][2] double, device;
+ *                a configuration with an invalid or absent species gets
+ *                {NaN, NaN}.
+ * Asynchronous on `stream`.
+ */
+pyhea_status pyhea_sro_eval_batch(const pyhea_lattice *lat, int64_t n_configs,
+                                  const int8_t *species_dev, const pyhea_objective *obj,
+                                  int32_t *counts_dev, double *S_F_dev, void *stream);
+
+/*
+ * Incremental evaluation of trial swaps against one configuration (Sec. 4.5,
+ * Eq. 4; Sec. 4.6.2, Eq. 5): for each pair (p, q) the count change dN of the
+ * swap and dS = S(after) - S(before) in the contract above, without applying
+ * the swap.  A pair with equal species gives dS = 0 and dN = 0.
+ *   pairs_dev  [n][2] int32 site ids, device.
+ *   dS_dev     [n] double, device.
+ *   dN_dev     [n][S][M][M] int32, device, or NULL.
+ * Asynchronous on `stream`.
+ */
+pyhea_status pyhea_trial_eval(const pyhea_lattice *lat, const pyhea_objective *obj,
+                              const int8_t *species_dev, int64_t n_pairs, const int32_t *pairs_dev,
+                              double *dS_dev, int32_t *dN_dev, void *stream);
+
+/*
+ * One Monte Carlo chain (Sec. 4.2, Algorithms 2-3; Sec. 4.6), run as one
+ * persistent kernel.  Every step draws B trial swaps from Philox4x32-10 with
+ * counter (slot, step, chain_id, 0): p = (x0 * N) >> 32, q = (x1 * N) >> 32;
+ * all are evaluated against the same configuration; improving swaps
+ * (dS < -tau) are ranked by (dS, slot) and committed by the commit mode:
+ * BEST commits the first; DISJOINT walks the ranking and commits every swap
+ * whose sites are not equal to, nor in shells 1..S of, a site already
+ * committed in the step, re-checking its dS against the updated state.
+ *   species_dev  [N] int8, device; initial configuration in, final out.
+ *   log_dev      [log_cap][4] uint32 (step, slot, p, q) per commit, device,
+ *                or NULL.
+ *   counts_host  [S][M][M] int64 final pair counts, or NULL.
+ * Synchronous.
+ */
+pyhea_status pyhea_mc_run(const pyhea_lattice *lat, const pyhea_objective *obj,
+                          const pyhea_mc_params *params, int8_t *species_dev, uint32_t *log_dev,
+                          int64_t log_cap, pyhea_mc_stats *stats_host, int64_t *counts_host,
+                          void *stream);
+
+/*
+ * Many independent chains of uneven geometry in one persistent launch
+ * (Sec. 4.6.1: one workgroup per candidate solution).  Arrays of length
+ * n_chains describe each chain; chain c owns species_dev[offsets_host[c] ..
+ * offsets_host[c+1]) and, if log_dev is not NULL, the records
+ * log_dev[log_offsets_host[c] .. log_offsets_host[c+1]).  Each chain's
+ * result is identical to pyhea_mc_run with the same inputs.  Launch shape is
+ * chosen by the autotuner (pyhea_tune_*), never the trajectory.
+ * Synchronous.
+ */
+pyhea_status pyhea_mc_batch(int32_t n_chains, const pyhea_lattice *lats,
+                            const pyhea_objective *objs, const pyhea_mc_params *params,
+                            int8_t *species_dev, const int64_t *offsets_host, uint32_t *log_dev,
+                            const int64_t *log_offsets_host, pyhea_mc_stats *stats_host,
+                            void *stream);
+
+/*
+ * Serving: a continuous-batching job server.  Jobs are single chains
+ * (pyhea_mc_run semantics, chain_id = job id); a worker thread admits queued
+ * jobs while free slots and the HBM budget allow, keeps their configurations
+ * and count tables resident on the device, advances all resident jobs in
+ * rounds of one persistent launch, and retires finished jobs as they end, so
+ * jobs that arrive while others run join the next round.
+ *   hbm_budget_bytes  device bytes the resident jobs may hold in total.
+ *   max_slots         jobs resident at once.
+ *   steps_per_round   MC steps per job per round (0 = library default).
+ */
+pyhea_status pyhea_serve_open(int64_t hbm_budget_bytes, int32_t max_slots,
+                              int32_t steps_per_round, void **server);
+
+/* Queue a job.  Inputs are copied; species_host is [N] int8.  The job's
+ * params->chain_id is replaced by job_id.  PYHEA_EINVAL for a malformed job or
+ * one that can never fit the HBM budget; duplicate ids are rejected. */
+pyhea_status pyhea_serve_submit(void *server, uint64_t job_id, const pyhea_lattice *lat,
+                                const pyhea_objective *obj, const pyhea_mc_params *params,
+                                const int8_t *species_host);
+
+/* Result of a finished job: species_out_host [N] int8 (or NULL) and stats.
+ * blocking = 0 returns PYHEA_EBUSY while the job runs; otherwise waits.
+ * times_ns_host (or NULL) receives {submit, admit, finish} on a monotonic
+ * clock.  A polled job is forgotten. */
+pyhea_status pyhea_serve_poll(void *server, uint64_t job_id, int8_t *species_out_host,
+                              pyhea_mc_stats *stats_host, int64_t *times_ns_host,
+                              int32_t blocking);
+
+/* Cancel a queued or running job (its poll then returns PYHEA_ECANCELLED). */
+pyhea_status pyhea_serve_cancel(void *server, uint64_t job_id);
+
+/* Server counters: {submitted, admitted, finished, rejected, resident, queued,
+ * rounds, bytes_resident}. */
+pyhea_status pyhea_serve_counters(void *server, int64_t *out8_host);
+
+/* Stop the worker, drop unfinished jobs and free the server. */
+pyhea_status pyhea_serve_close(void *server);
+
+/* Philox4x32-10 (Salmon et al., SC'11) on the device, for checking the
+ * library's trial draws: out[i] = philox(ctr[i], key = (lo32(seed), hi32(seed))).
+ * ctr_dev and out_dev are [n][4] uint32, device.  Asynchronous. */
+pyhea_status pyhea_philox4x32_10(const uint32_t *ctr_dev, uint64_t seed, int64_t n,
+                                 uint32_t *out_dev, void *stream);
+
+/* Autotuner: file that caches tuned launch shapes (NULL = no persistence), and
+ * a switch to force one shape (-1 = tuned).  Shapes never change results. */
+pyhea_status pyhea_tune_set_cache(const char *path);
+pyhea_status pyhea_tune_force(int32_t variant);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PYHEA_H */

@@ -1,0 +1,243 @@
+"""Thin ctypes binding of libpyhea (include/pyhea.h).
+
+Functions carry the C names and only marshal arguments: torch tensors become
+device pointers, numpy arrays become host pointers, and the current torch
+stream is passed as the HIP stream.  Every computation runs in the HIP
+library; if the library is missing this module raises instead of falling
+back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpyhea.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EBUSY, ECANCELLED, ENOSYS, ENOENT = 0, -1, -2, -3, -4, -5, -6, -7
+FCC, BCC = 0, 1
+MODE_DISJOINT, MODE_BEST = 0, 1
+
+EXPORTS = [
+    "pyhea_version", "pyhea_last_error", "pyhea_sro_eval", "pyhea_sro_eval_batch",
+    "pyhea_trial_eval", "pyhea_mc_run", "pyhea_mc_batch", "pyhea_serve_open",
+    "pyhea_serve_submit", "pyhea_serve_poll", "pyhea_serve_cancel", "pyhea_serve_counters",
+    "pyhea_serve_close", "pyhea_philox4x32_10", "pyhea_tune_set_cache", "pyhea_tune_force",
+]
+
+
+class PyheaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pyhea error {code}: {msg}")
+        self.code = code
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int32), ("L", ctypes.c_int32 * 3),
+                ("n_species", ctypes.c_int32), ("n_shells", ctypes.c_int32)]
+
+
+class Objective(ctypes.Structure):
+    _fields_ = [("target", ctypes.c_void_p), ("weight", ctypes.c_void_p)]
+
+
+class McParams(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("chain_id", ctypes.c_uint32),
+                ("cand_per_step", ctypes.c_int32), ("n_trials", ctypes.c_int64),
+                ("commit_mode", ctypes.c_int32), ("depth_limit", ctypes.c_int32),
+                ("accept_tol", ctypes.c_double)]
+
+
+class McStats(ctypes.Structure):
+    _fields_ = [("trials", ctypes.c_int64), ("null_trials", ctypes.c_int64),
+                ("commits", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("stop_reason", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("S", ctypes.c_double), ("F", ctypes.c_double), ("log_len", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libpyhea.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        sig = {
+            "pyhea_version": ([], i32),
+            "pyhea_last_error": ([], ctypes.c_char_p),
+            "pyhea_sro_eval": ([P, P, P, P, P, P, P], i32),
+            "pyhea_sro_eval_batch": ([P, i64, P, P, P, P, P], i32),
+            "pyhea_trial_eval": ([P, P, P, i64, P, P, P, P], i32),
+            "pyhea_mc_run": ([P, P, P, P, P, i64, P, P, P], i32),
+            "pyhea_mc_batch": ([i32, P, P, P, P, P, P, P, P, P], i32),
+            "pyhea_serve_open": ([i64, i32, i32, P], i32),
+            "pyhea_serve_submit": ([P, u64, P, P, P, P], i32),
+            "pyhea_serve_poll": ([P, u64, P, P, P, i32], i32),
+            "pyhea_serve_cancel": ([P, u64], i32),
+            "pyhea_serve_counters": ([P, P], i32),
+            "pyhea_serve_close": ([P], i32),
+            "pyhea_philox4x32_10": ([P, u64, i64, P, P], i32),
+            "pyhea_tune_set_cache": ([ctypes.c_char_p], i32),
+            "pyhea_tune_force": ([i32], i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != OK:
+        raise PyheaError(code, lib().pyhea_last_error().decode())
+    return code
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t, dtype=None):
+    """Device pointer of a contiguous torch tensor on the GPU."""
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _hptr(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def make_lattice(lattice: int, L, M: int, S: int) -> Lattice:
+    return Lattice(lattice, (ctypes.c_int32 * 3)(*[int(x) for x in L]), M, S)
+
+
+class _Obj:
+    """Objective with its host arrays kept alive."""
+
+    def __init__(self, target, weight, S: int, M: int):
+        self.t = np.ascontiguousarray(np.asarray(target, dtype=np.float64).reshape(S, M, M))
+        self.w = np.ascontiguousarray(np.asarray(weight, dtype=np.float64).reshape(S))
+        self.c = Objective(_hptr(self.t), _hptr(self.w))
+
+
+def make_params(seed: int, chain_id: int, n_trials: int, B: int = 64, mode: int = MODE_DISJOINT,
+                depth_limit: int = 0, tau: float = 0.0) -> McParams:
+    return McParams(seed, chain_id, B, n_trials, mode, depth_limit, tau)
+
+
+# --------------------------------------------------------------------------- API
+
+def pyhea_version() -> int:
+    return int(lib().pyhea_version())
+
+
+def pyhea_sro_eval(lattice: int, L, M: int, S: int, species, target=None, weight=None,
+                   stream=None):
+    """Full evaluation of one configuration: (counts int64, alpha, S, F)."""
+    import torch
+    lat = make_lattice(lattice, L, M, S)
+    counts = np.zeros((S, M, M), np.int64)
+    alpha = np.zeros((S, M, M))
+    sf = np.zeros(2)
+    obj = _Obj(target, weight, S, M) if target is not None else None
+    _check(lib().pyhea_sro_eval(ctypes.byref(lat), _dptr(species, torch.int8),
+                                ctypes.byref(obj.c) if obj else None, _hptr(counts), _hptr(alpha),
+                                _hptr(sf), _stream(stream)))
+    return counts, alpha, (float(sf[0]) if obj else None), (float(sf[1]) if obj else None)
+
+
+def pyhea_sro_eval_batch(lattice: int, L, M: int, S: int, species, counts, target=None,
+                         weight=None, S_F=None, stream=None):
+    """Full evaluation of K configurations species[K][N] into counts[K][S][M][M]
+    (int32) and optionally S_F[K][2]; asynchronous on the stream."""
+    import torch
+    lat = make_lattice(lattice, L, M, S)
+    K = species.shape[0]
+    obj = _Obj(target, weight, S, M) if target is not None else None
+    _check(lib().pyhea_sro_eval_batch(ctypes.byref(lat), K, _dptr(species, torch.int8),
+                                      ctypes.byref(obj.c) if obj else None,
+                                      _dptr(counts, torch.int32),
+                                      _dptr(S_F, torch.float64) if S_F is not None else None,
+                                      _stream(stream)))
+
+
+def pyhea_trial_eval(lattice: int, L, M: int, S: int, species, target, weight, pairs, dS,
+                     dN=None, stream=None):
+    import torch
+    lat = make_lattice(lattice, L, M, S)
+    obj = _Obj(target, weight, S, M)
+    _check(lib().pyhea_trial_eval(ctypes.byref(lat), ctypes.byref(obj.c), _dptr(species, torch.int8),
+                                  pairs.shape[0], _dptr(pairs, torch.int32), _dptr(dS, torch.float64),
+                                  _dptr(dN, torch.int32) if dN is not None else None,
+                                  _stream(stream)))
+
+
+def pyhea_mc_run(lattice: int, L, M: int, S: int, target, weight, species, params: McParams,
+                 log=None, stream=None):
+    """One chain; species (device int8 [N]) is updated in place.  Returns
+    (stats dict, final counts int64 [S][M][M])."""
+    import torch
+    lat = make_lattice(lattice, L, M, S)
+    obj = _Obj(target, weight, S, M)
+    st = McStats()
+    counts = np.zeros((S, M, M), np.int64)
+    cap = 0 if log is None else log.shape[0]
+    _check(lib().pyhea_mc_run(ctypes.byref(lat), ctypes.byref(obj.c), ctypes.byref(params),
+                              _dptr(species, torch.int8),
+                              _dptr(log, torch.int32) if log is not None else None, cap,
+                              ctypes.byref(st), _hptr(counts), _stream(stream)))
+    return st.as_dict(), counts
+
+
+def pyhea_mc_batch(problems, species, offsets, params_list, log=None, log_offsets=None,
+                   stream=None):
+    """Many chains in one call.  problems: list of (lattice, L, M, S, target,
+    weight); species: device int8, chains concatenated; offsets: [n+1] int64.
+    Returns a list of stats dicts."""
+    import torch
+    n = len(problems)
+    lats = (Lattice * n)(*[make_lattice(p[0], p[1], p[2], p[3]) for p in problems])
+    keep = [_Obj(p[4], p[5], p[3], p[2]) for p in problems]
+    objs = (Objective * n)(*[k.c for k in keep])
+    pars = (McParams * n)(*params_list)
+    stats = (McStats * n)()
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    loff = None if log_offsets is None else np.ascontiguousarray(np.asarray(log_offsets, np.int64))
+    _check(lib().pyhea_mc_batch(n, lats, objs, pars, _dptr(species, torch.int8), _hptr(off),
+                                _dptr(log, torch.int32) if log is not None else None,
+                                _hptr(loff), stats, _stream(stream)))
+    return [s.as_dict() for s in stats]
+
+
+def pyhea_philox4x32_10(ctr, seed: int, out, stream=None):
+    import torch
+    _check(lib().pyhea_philox4x32_10(_dptr(ctr, torch.int32), seed, ctr.shape[0],
+                                     _dptr(out, torch.int32), _stream(stream)))
+
+
+def pyhea_tune_force(variant: int):
+    _check(lib().pyhea_tune_force(variant))
+
+
+def pyhea_tune_set_cache(path: str | None):
+    _check(lib().pyhea_tune_set_cache(None if path is None else path.encode()))

@@ -1,0 +1,283 @@
+// C ABI of the pyhea library (see include/pyhea.h for the contract of every
+// entry point).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "autotune.h"
+#include "pyhea.h"
+#include "runtime.h"
+
+namespace pyhea {
+const std::string &last_error();
+}
+
+using namespace pyhea;
+
+namespace {
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+struct AsyncBuffer {
+    void *ptr = nullptr;
+    hipStream_t stream = nullptr;
+    ~AsyncBuffer() {
+        if (ptr) (void)hipFreeAsync(ptr, stream);
+    }
+};
+
+pyhea_status guard(pyhea_status s) {
+    if (s == PYHEA_OK) set_error("");
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pyhea_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+
+const char *pyhea_last_error(void) { return pyhea::last_error().c_str(); }
+
+pyhea_status pyhea_sro_eval(const pyhea_lattice *lat, const int8_t *species_dev, const pyhea_objective *obj,
+                            int64_t *counts_host, double *alpha_host, double *S_F_host, void *stream_) {
+    Geometry g;
+    std::string err;
+    if (build_geometry(lat, &g, &err) != PYHEA_OK) {
+        set_error(err);
+        return PYHEA_EINVAL;
+    }
+    if (!species_dev) {
+        set_error("species_dev must not be NULL");
+        return PYHEA_EINVAL;
+    }
+    if (obj) {
+        const pyhea_status s = check_objective(g, obj);
+        if (s != PYHEA_OK) return s;
+    }
+    hipStream_t stream = as_stream(stream_);
+    const int E = g.S * g.M * g.M;
+    AsyncBuffer buf;
+    buf.stream = stream;
+    PYHEA_HIP(hipMallocAsync(&buf.ptr, E * 4 + 256, stream));
+    int32_t *counts = (int32_t *)buf.ptr;
+    int32_t *bad = (int32_t *)((char *)buf.ptr + ((E * 4 + 127) & ~127));
+    EvalDesc ed;
+    fill_eval_desc(g, &ed);
+    PYHEA_HIP(launch_count_gather(ed, 1, species_dev, counts, bad, stream));
+    std::vector<int32_t> c32(E);
+    int32_t badh = 0;
+    PYHEA_HIP(hipMemcpyAsync(c32.data(), counts, E * 4, hipMemcpyDeviceToHost, stream));
+    PYHEA_HIP(hipMemcpyAsync(&badh, bad, 4, hipMemcpyDeviceToHost, stream));
+    PYHEA_HIP(hipStreamSynchronize(stream));
+    std::vector<int64_t> c64(c32.begin(), c32.end());
+    int64_t n[kMaxSpecies];
+    if (badh || !species_totals(g, c64.data(), n)) {
+        set_error("species ids must lie in [0, n_species) and every species must occur");
+        return PYHEA_EINVAL;
+    }
+    if (counts_host) std::memcpy(counts_host, c64.data(), E * 8);
+    double SF[2];
+    host_objective(g, c64.data(), obj ? obj->target : nullptr, obj ? obj->weight : nullptr, alpha_host,
+                   SF);
+    if (obj && S_F_host) {
+        S_F_host[0] = SF[0];
+        S_F_host[1] = SF[1];
+    }
+    return guard(PYHEA_OK);
+}
+
+pyhea_status pyhea_sro_eval_batch(const pyhea_lattice *lat, int64_t n_configs, const int8_t *species_dev,
+                                  const pyhea_objective *obj, int32_t *counts_dev, double *S_F_dev,
+                                  void *stream_) {
+    Geometry g;
+    std::string err;
+    if (build_geometry(lat, &g, &err) != PYHEA_OK) {
+        set_error(err);
+        return PYHEA_EINVAL;
+    }
+    if (n_configs < 0 || (n_configs > 0 && (!species_dev || !counts_dev))) {
+        set_error("n_configs must be >= 0 and species_dev/counts_dev non-NULL");
+        return PYHEA_EINVAL;
+    }
+    if ((obj == nullptr) != (S_F_dev == nullptr)) {
+        set_error("obj and S_F_dev must be given together");
+        return PYHEA_EINVAL;
+    }
+    if (obj) {
+        const pyhea_status s = check_objective(g, obj);
+        if (s != PYHEA_OK) return s;
+    }
+    if (n_configs == 0) return guard(PYHEA_OK);
+    hipStream_t stream = as_stream(stream_);
+    const int E = g.S * g.M * g.M;
+    AsyncBuffer buf;
+    buf.stream = stream;
+    const size_t bad_bytes = (size_t)n_configs * 4;
+    const size_t tw_off = (bad_bytes + 255) & ~size_t(255);
+    PYHEA_HIP(hipMallocAsync(&buf.ptr, tw_off + (E + kMaxShells) * 8, stream));
+    int32_t *bad = (int32_t *)buf.ptr;
+    double *tdev = (double *)((char *)buf.ptr + tw_off);
+    EvalDesc ed;
+    fill_eval_desc(g, &ed);
+    PYHEA_HIP(launch_count_gather(ed, n_configs, species_dev, counts_dev, bad, stream));
+    if (obj) {
+        std::vector<double> tw(E + kMaxShells, 0.0);
+        std::memcpy(tw.data(), obj->target, E * 8);
+        std::memcpy(tw.data() + E, obj->weight, g.S * 8);
+        PYHEA_HIP(hipMemcpyAsync(tdev, tw.data(), tw.size() * 8, hipMemcpyHostToDevice, stream));
+        PYHEA_HIP(launch_objective_epilogue(ed, n_configs, counts_dev, bad, tdev, tdev + E, S_F_dev, stream));
+        PYHEA_HIP(hipStreamSynchronize(stream));  // tw is host memory
+    }
+    return guard(PYHEA_OK);
+}
+
+pyhea_status pyhea_trial_eval(const pyhea_lattice *lat, const pyhea_objective *obj, const int8_t *species_dev,
+                              int64_t n_pairs, const int32_t *pairs_dev, double *dS_dev, int32_t *dN_dev,
+                              void *stream_) {
+    Geometry g;
+    std::string err;
+    if (build_geometry(lat, &g, &err) != PYHEA_OK) {
+        set_error(err);
+        return PYHEA_EINVAL;
+    }
+    pyhea_status s = check_objective(g, obj);
+    if (s != PYHEA_OK) return s;
+    if (n_pairs < 0 || !species_dev || (n_pairs > 0 && (!pairs_dev || !dS_dev))) {
+        set_error("n_pairs must be >= 0 and species/pairs/dS pointers non-NULL");
+        return PYHEA_EINVAL;
+    }
+    hipStream_t stream = as_stream(stream_);
+    const int E = g.S * g.M * g.M;
+    AsyncBuffer buf;
+    buf.stream = stream;
+    PYHEA_HIP(hipMallocAsync(&buf.ptr, 256 + E * 4 + (E + kMaxShells) * 8 + 256, stream));
+    int32_t *bad = (int32_t *)buf.ptr;
+    int32_t *counts = (int32_t *)((char *)buf.ptr + 256);
+    double *tdev = (double *)((char *)buf.ptr + 256 + ((E * 4 + 255) & ~255));
+    EvalDesc ed;
+    fill_eval_desc(g, &ed);
+    PYHEA_HIP(launch_count_gather(ed, 1, species_dev, counts, bad, stream));
+    std::vector<int32_t> c32(E);
+    int32_t badh = 0;
+    PYHEA_HIP(hipMemcpyAsync(c32.data(), counts, E * 4, hipMemcpyDeviceToHost, stream));
+    PYHEA_HIP(hipMemcpyAsync(&badh, bad, 4, hipMemcpyDeviceToHost, stream));
+    PYHEA_HIP(hipStreamSynchronize(stream));
+    std::vector<int64_t> c64(c32.begin(), c32.end());
+    int64_t n[kMaxSpecies];
+    if (badh || !species_totals(g, c64.data(), n)) {
+        set_error("species ids must lie in [0, n_species) and every species must occur");
+        return PYHEA_EINVAL;
+    }
+    std::vector<double> tw(E + kMaxShells, 0.0);
+    std::memcpy(tw.data(), obj->target, E * 8);
+    std::memcpy(tw.data() + E, obj->weight, g.S * 8);
+    PYHEA_HIP(hipMemcpyAsync(tdev, tw.data(), tw.size() * 8, hipMemcpyHostToDevice, stream));
+    PYHEA_HIP(launch_trial_eval(ed, species_dev, counts, tdev, tdev + E, n_pairs, pairs_dev, dS_dev, dN_dev,
+                                stream));
+    PYHEA_HIP(hipStreamSynchronize(stream));
+    return guard(PYHEA_OK);
+}
+
+static pyhea_status make_job(const pyhea_lattice *lat, const pyhea_objective *obj, const pyhea_mc_params *params,
+                             ChainJob *job, const char *who) {
+    std::string err;
+    if (build_geometry(lat, &job->g, &err) != PYHEA_OK) {
+        set_error(std::string(who) + err);
+        return PYHEA_EINVAL;
+    }
+    pyhea_status s = check_objective(job->g, obj);
+    if (s != PYHEA_OK) return s;
+    s = check_params(params);
+    if (s != PYHEA_OK) return s;
+    job->params = *params;
+    const int E = job->g.S * job->g.M * job->g.M;
+    job->target.assign(obj->target, obj->target + E);
+    job->weight.assign(obj->weight, obj->weight + job->g.S);
+    return PYHEA_OK;
+}
+
+pyhea_status pyhea_mc_run(const pyhea_lattice *lat, const pyhea_objective *obj, const pyhea_mc_params *params,
+                          int8_t *species_dev, uint32_t *log_dev, int64_t log_cap, pyhea_mc_stats *stats_host,
+                          int64_t *counts_host, void *stream) {
+    std::vector<ChainJob> jobs(1);
+    pyhea_status s = make_job(lat, obj, params, &jobs[0], "");
+    if (s != PYHEA_OK) return s;
+    if (!species_dev || !stats_host || log_cap < 0) {
+        set_error("species_dev and stats_host must not be NULL; log_cap >= 0");
+        return PYHEA_EINVAL;
+    }
+    jobs[0].species_dev = species_dev;
+    jobs[0].log_dev = log_dev;
+    jobs[0].log_cap = log_cap;
+    std::vector<std::vector<int64_t>> fc;
+    s = run_chains(jobs, stats_host, &fc, as_stream(stream), forced_variant());
+    if (s != PYHEA_OK) return s;
+    if (counts_host) std::memcpy(counts_host, fc[0].data(), fc[0].size() * 8);
+    return guard(PYHEA_OK);
+}
+
+pyhea_status pyhea_mc_batch(int32_t n_chains, const pyhea_lattice *lats, const pyhea_objective *objs,
+                            const pyhea_mc_params *params, int8_t *species_dev, const int64_t *offsets_host,
+                            uint32_t *log_dev, const int64_t *log_offsets_host, pyhea_mc_stats *stats_host,
+                            void *stream) {
+    if (n_chains < 0 || (n_chains > 0 && (!lats || !objs || !params || !species_dev || !offsets_host ||
+                                          !stats_host))) {
+        set_error("n_chains must be >= 0 and the descriptor arrays non-NULL");
+        return PYHEA_EINVAL;
+    }
+    if (log_dev && !log_offsets_host) {
+        set_error("log_offsets_host is required with log_dev");
+        return PYHEA_EINVAL;
+    }
+    std::vector<ChainJob> jobs(n_chains);
+    for (int c = 0; c < n_chains; ++c) {
+        const std::string who = "chain " + std::to_string(c) + ": ";
+        pyhea_status s = make_job(&lats[c], &objs[c], &params[c], &jobs[c], who.c_str());
+        if (s != PYHEA_OK) return s;
+        if (offsets_host[c + 1] - offsets_host[c] != jobs[c].g.N || offsets_host[c] < 0) {
+            set_error(who + "offsets do not match the chain's site count");
+            return PYHEA_EINVAL;
+        }
+        jobs[c].species_dev = species_dev + offsets_host[c];
+        if (log_dev) {
+            jobs[c].log_dev = log_dev + 4 * log_offsets_host[c];
+            jobs[c].log_cap = log_offsets_host[c + 1] - log_offsets_host[c];
+            if (jobs[c].log_cap < 0) {
+                set_error(who + "log offsets must be non-decreasing");
+                return PYHEA_EINVAL;
+            }
+        }
+    }
+    pyhea_status s = run_chains(jobs, stats_host, nullptr, as_stream(stream), forced_variant());
+    return s == PYHEA_OK ? guard(s) : s;
+}
+
+pyhea_status pyhea_philox4x32_10(const uint32_t *ctr_dev, uint64_t seed, int64_t n, uint32_t *out_dev,
+                                 void *stream) {
+    if (n < 0 || (n > 0 && (!ctr_dev || !out_dev))) {
+        set_error("n must be >= 0 and pointers non-NULL");
+        return PYHEA_EINVAL;
+    }
+    PYHEA_HIP(launch_philox(ctr_dev, seed, n, out_dev, as_stream(stream)));
+    return guard(PYHEA_OK);
+}
+
+pyhea_status pyhea_tune_set_cache(const char *path) {
+    set_tune_cache_path(path);
+    return guard(PYHEA_OK);
+}
+
+pyhea_status pyhea_tune_force(int32_t variant) {
+    if (variant < -1 || variant >= kNumStoreVariants) {
+        set_error("variant out of range");
+        return PYHEA_EINVAL;
+    }
+    set_forced_variant(variant);
+    return guard(PYHEA_OK);
+}
+
+}  // extern "C"

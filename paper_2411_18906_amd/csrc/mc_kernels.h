@@ -1,0 +1,66 @@
+// Launchers of the pyhea kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "geometry.h"
+
+namespace pyhea {
+
+// LDS layout of the MC kernel (must match the carve order in mc_kernels.hip).
+__host__ __device__ inline int mc_lds_bytes(int S, int M, int B) {
+    auto r = [](int b) { return (b + 15) & ~15; };
+    const int E = S * M * M;
+    int n = 0;
+    n += r(E * 4) + 3 * r(E * 8);                 // cnt, sqv, Rv, tv
+    n += r(4 * kMaxOffsets * 4) + r(kMaxOffsets * 4);  // dlin, offmod
+    n += r(B * 8) + 5 * r(B * 4);                 // rec_dS, p, q, pp, pq, ab
+    n += 3 * r(S * B * 8);                        // rec_cp, rec_cq, rec_dQ
+    n += 2 * r(B * 4) + r(2 * B * 4);             // order, list, cpos
+    n += r(kMaxShells * 8) + r(16 * 4);           // sh_dQ, sh_int
+    return n;
+}
+
+// bytes of the species store for a padded chain
+inline int64_t species_store_bytes(int store, int64_t Npad) {
+    if (store == kStoreLds8) return (Npad + 15) & ~int64_t(15);
+    if (store == kStoreLds4) return (((Npad + 7) / 8) * 4 + 15) & ~int64_t(15);
+    return 0;
+}
+
+int mc_block_threads(int S, int B);
+hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, bool wide, int S, int B,
+                     int lds_bytes, int max_steps, hipStream_t stream);
+hipError_t launch_pad_fill(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);
+hipError_t launch_pad_drain(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);
+
+// Full evaluation: pair counts of K configurations of one geometry.
+struct EvalDesc {
+    int32_t A, lgA, Lx, Ly, Lz, M, S;
+    int32_t n_half;                       // offsets with one of each +-d pair
+    int32_t z0;                           // coordination number of shell 1
+    int32_t zk[kMaxShells];
+    double inv_Lx, inv_Ly;
+    uint32_t N;
+    int32_t Z;                            // all offsets of shells 1..S
+    // per (basis, half offset): dcx, dcy, dcz, target basis, shell (int8 each)
+    int8_t half[4][kMaxOffsets / 2][5];
+    int8_t off[kMaxOffsets][4];           // dx, dy, dz, shell (half units)
+};
+
+void fill_eval_desc(const Geometry &g, EvalDesc *d);
+
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t stream);
+
+hipError_t launch_count_gather(const EvalDesc &ed, int64_t K, const int8_t *species,
+                               int32_t *counts, int32_t *bad, hipStream_t stream);
+hipError_t launch_objective_epilogue(const EvalDesc &ed, int64_t K, const int32_t *counts,
+                                     const int32_t *bad, const double *target, const double *weight,
+                                     double *S_F, hipStream_t stream);
+hipError_t launch_trial_eval(const EvalDesc &ed, const int8_t *species, const int32_t *counts,
+                             const double *target, const double *weight, int64_t n_pairs,
+                             const int32_t *pairs, double *dS, int32_t *dN, hipStream_t stream);
+hipError_t launch_philox(const uint32_t *ctr, uint64_t seed, int64_t n, uint32_t *out,
+                         hipStream_t stream);
+
+}  // namespace pyhea

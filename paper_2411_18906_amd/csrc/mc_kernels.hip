@@ -1,0 +1,574 @@
+// Persistent Monte Carlo kernel: SRO-targeted swap search (Sec. 4.2,
+// Algorithm 3; Sec. 4.5-4.6).
+//
+// One workgroup runs one chain for up to `max_steps` steps.  The workgroup has
+// G * S wavefronts (G = ceil(B / 64) slot groups, S shells); wave w = g * S + k
+// evaluates shell k of slots g*64 .. g*64+63, so every wave has a uniform shell
+// and its loops over offsets and (i, j) entries are uniform.
+//
+// Per step:
+//  1. every (slot, shell) lane draws the slot's swap (Philox4x32-10, counter
+//     (slot, step, chain, 0)), gathers the species of the z_k shell-k
+//     neighbours of both sites from the halo-padded configuration (one linear
+//     delta per (basis, offset), no modulo), removes the partner site, and
+//     forms D = c_q - c_p and dQ_k = sum_{i,j} sq(N + dN) - sq(N) (Eq. 4-5);
+//  2. wave 0 sums dS = sum_k w_k dQ_k per slot, compacts the improving slots
+//     (dS < -tau) and ranks them by (dS, slot) (Eq. 6);
+//  3. all waves walk the ranking in lock step: BEST stops after one commit;
+//     DISJOINT skips swaps within shells 1..S of a site already committed in
+//     the step and re-checks dS against the updated counts before committing.
+// Counts are exact int32; every binary64 value is produced by the same
+// expression sequence as the host contract, with contraction disabled.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "mc_kernels.h"
+
+namespace pyhea {
+
+namespace {
+
+template <bool kWide>
+struct HistT {
+    using type = uint32_t;
+};
+template <>
+struct HistT<true> {
+    using type = uint64_t;
+};
+
+// 5-bit fields: z_k <= 24 neighbours of one species per shell
+template <typename H>
+__device__ __forceinline__ int fld(H h, int j) {
+    return (int)((h >> (5 * j)) & 31u);
+}
+template <typename H>
+__device__ __forceinline__ H one_at(int j) {
+    return (H)1 << (5 * j);
+}
+
+// dN[i][j] of swapping species a (at p) and b (at q), a != b (Eq. 4 in count
+// form): rows/columns a and b change by +-D, the diagonal by 2D, (a,b) by
+// D[b] - D[a]; all other entries are unchanged.
+__device__ __forceinline__ int swap_dn(int i, int j, int a, int b, int Di, int Dj, int Da, int Db) {
+    if (i == a) return j == a ? 2 * Da : (j == b ? Db - Da : Dj);
+    if (i == b) return j == b ? -2 * Db : (j == a ? Db - Da : -Dj);
+    if (j == a) return Di;
+    if (j == b) return -Di;
+    return 0;
+}
+
+__device__ __forceinline__ double sq_dev(int32_t n, double R, double t) {
+    const double alpha = 1.0 - (double)n * R;
+    const double d = alpha - t;
+    return d * d;
+}
+
+struct Lds {
+    int32_t *cnt;   // [S][M][M]
+    double *sqv;    // [S][M][M]
+    double *Rv;     // [S][M][M]
+    double *tv;     // [S][M][M]
+    int32_t *dlin;  // [4][kMaxOffsets]
+    int32_t *offmod;
+    double *rec_dS;     // [B]
+    uint32_t *rec_p;    // [B]
+    uint32_t *rec_q;    // [B]
+    uint32_t *rec_pp;   // [B] packed position of p (10 bits per axis)
+    uint32_t *rec_pq;   // [B]
+    uint32_t *rec_ab;   // [B] a | b << 8 | null << 16
+    uint64_t *rec_cp;   // [S][B]
+    uint64_t *rec_cq;   // [S][B]
+    double *rec_dQ;     // [S][B]
+    int32_t *order;     // [B]
+    int32_t *list;      // [B]
+    uint32_t *cpos;     // [2B] committed site positions
+    double *sh_dQ;      // [kMaxShells]
+    int32_t *sh_int;    // scalars
+    uint8_t *store;     // species store
+};
+
+__device__ __forceinline__ uint8_t *carve(uint8_t *&p, size_t bytes) {
+    uint8_t *r = p;
+    p += (bytes + 15) & ~size_t(15);
+    return r;
+}
+
+template <int kStore>
+__device__ __forceinline__ int load_species(const Lds &L, const ChainDesc &d, int32_t pid) {
+    if constexpr (kStore == kStoreLds8) {
+        return L.store[pid];
+    } else if constexpr (kStore == kStoreLds4) {
+        const uint32_t w = reinterpret_cast<const uint32_t *>(L.store)[pid >> 3];
+        return (int)((w >> ((pid & 7) << 2)) & 0xFu);
+    } else {
+        return d.pad_global[pid];
+    }
+}
+
+template <int kStore>
+__device__ __forceinline__ void store_species(const Lds &L, const ChainDesc &d, int32_t pid, int v) {
+    if constexpr (kStore == kStoreLds8) {
+        L.store[pid] = (uint8_t)v;
+    } else if constexpr (kStore == kStoreLds4) {
+        uint32_t *w = reinterpret_cast<uint32_t *>(L.store) + (pid >> 3);
+        const int sh = (pid & 7) << 2;
+        atomicAnd(w, ~(0xFu << sh));
+        atomicOr(w, (uint32_t)v << sh);
+    } else {
+        d.pad_global[pid] = (int8_t)v;
+    }
+}
+
+__device__ __forceinline__ int32_t padded_id(const ChainDesc &d, int px, int py, int pz, int b) {
+    return ((pz * d.PY + py) * d.PX + px) * d.A + b;
+}
+
+__device__ __forceinline__ int wrap_axis(int v, int L) {
+    while (v < 0) v += L;
+    while (v >= L) v -= L;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t pack_pos(int x, int y, int z) {
+    return (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
+}
+
+// squared minimum-image distance (half units) between two packed positions
+__device__ __forceinline__ int min_image_r2(const ChainDesc &d, uint32_t u, uint32_t v) {
+    const int Ls[3] = {d.Lx, d.Ly, d.Lz};
+    int r2 = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int x = (int)((u >> (10 * a)) & 1023u) - (int)((v >> (10 * a)) & 1023u);
+        const int box = 2 * Ls[a];
+        if (x > Ls[a]) x -= box;
+        if (x < -Ls[a]) x += box;
+        r2 += x * x;
+    }
+    return r2;
+}
+
+// the packed (pos_q - pos_p) mod box, for the exact multiplicity count on small cells
+__device__ __forceinline__ int32_t mod_delta(const ChainDesc &d, uint32_t pp, uint32_t pq) {
+    const int Ls[3] = {d.Lx, d.Ly, d.Lz};
+    int32_t out = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int x = (int)((pq >> (10 * a)) & 1023u) - (int)((pp >> (10 * a)) & 1023u);
+        if (x < 0) x += 2 * Ls[a];
+        out |= x << (10 * a);
+    }
+    return out;
+}
+
+// does a site at packed position u lie on, or in shells 1..S of, position v?
+__device__ __forceinline__ bool near_or_equal(const ChainDesc &d, uint32_t u, uint32_t v) {
+    const int r2 = min_image_r2(d, u, v);
+    if (r2 == 0) return true;
+    bool hit = false;
+#pragma unroll
+    for (int k = 0; k < kMaxShells; ++k) hit |= (k < d.S && r2 == d.r2[k]);
+    return hit;
+}
+
+// write species v at site (cx, cy, cz, b) and at every halo copy of it
+template <int kStore>
+__device__ void write_site(const Lds &L, const ChainDesc &d, int cx, int cy, int cz, int b, int v,
+                           int lane) {
+    const int h = d.halo;
+    const int x0 = wrap_axis(cx + h, d.Lx), y0 = wrap_axis(cy + h, d.Ly), z0 = wrap_axis(cz + h, d.Lz);
+    const int nx = (d.PX - 1 - x0) / d.Lx + 1;
+    const int ny = (d.PY - 1 - y0) / d.Ly + 1;
+    const int nz = (d.PZ - 1 - z0) / d.Lz + 1;
+    const int total = nx * ny * nz;
+    for (int t = lane; t < total; t += kWave) {
+        const int ix = t % nx, iy = (t / nx) % ny, iz = t / (nx * ny);
+        store_species<kStore>(L, d, padded_id(d, x0 + ix * d.Lx, y0 + iy * d.Ly, z0 + iz * d.Lz, b), v);
+    }
+}
+
+template <int kStore, bool kWide>
+__global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ descs,
+                                                  int32_t max_steps) {
+    using Hist = typename HistT<kWide>::type;
+    const ChainDesc &d = descs[blockIdx.x];
+    ChainState *st = d.state;
+    if (st->done) return;
+
+    const int S = d.S, M = d.M, E = S * M * M;
+    const int B = d.B;
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int k = wave % S;     // shell handled by this wave
+    const int grp = wave / S;   // slot group
+    const int slot = grp * kWave + lane;
+    const int nthreads = blockDim.x;
+
+    extern __shared__ __align__(16) uint8_t smem[];
+    Lds L;
+    {
+        uint8_t *p = smem;
+        L.cnt = (int32_t *)carve(p, E * 4);
+        L.sqv = (double *)carve(p, E * 8);
+        L.Rv = (double *)carve(p, E * 8);
+        L.tv = (double *)carve(p, E * 8);
+        L.dlin = (int32_t *)carve(p, 4 * kMaxOffsets * 4);
+        L.offmod = (int32_t *)carve(p, kMaxOffsets * 4);
+        L.rec_dS = (double *)carve(p, B * 8);
+        L.rec_p = (uint32_t *)carve(p, B * 4);
+        L.rec_q = (uint32_t *)carve(p, B * 4);
+        L.rec_pp = (uint32_t *)carve(p, B * 4);
+        L.rec_pq = (uint32_t *)carve(p, B * 4);
+        L.rec_ab = (uint32_t *)carve(p, B * 4);
+        L.rec_cp = (uint64_t *)carve(p, S * B * 8);
+        L.rec_cq = (uint64_t *)carve(p, S * B * 8);
+        L.rec_dQ = (double *)carve(p, S * B * 8);
+        L.order = (int32_t *)carve(p, B * 4);
+        L.list = (int32_t *)carve(p, B * 4);
+        L.cpos = (uint32_t *)carve(p, 2 * B * 4);
+        L.sh_dQ = (double *)carve(p, kMaxShells * 8);
+        L.sh_int = (int32_t *)carve(p, 16 * 4);
+        L.store = p;
+    }
+
+    // ---- load chain state into LDS ------------------------------------------------
+    for (int e = threadIdx.x; e < E; e += nthreads) {
+        L.cnt[e] = d.counts[e];
+        L.Rv[e] = d.R[e];
+        L.tv[e] = d.target[e];
+        L.sqv[e] = sq_dev(L.cnt[e], L.Rv[e], L.tv[e]);
+    }
+    for (int t = threadIdx.x; t < 4 * kMaxOffsets; t += nthreads) L.dlin[t] = d.dlin[t / kMaxOffsets][t % kMaxOffsets];
+    for (int t = threadIdx.x; t < kMaxOffsets; t += nthreads) L.offmod[t] = d.off_mod[t];
+    if constexpr (kStore != kStoreGlobal) {
+        // fill the halo-padded configuration from the unpadded one
+        const double inv_PX = 1.0 / (double)d.PX, inv_PY = 1.0 / (double)d.PY;
+        const int h = d.halo;
+        if constexpr (kStore == kStoreLds8) {
+            for (uint32_t pid = threadIdx.x; pid < d.Npad; pid += nthreads) {
+                const SiteCoord c = site_coord(pid, d.lgA, d.PX, d.PY, inv_PX, inv_PY);
+                const int cx = wrap_axis(c.cx - h, d.Lx), cy = wrap_axis(c.cy - h, d.Ly),
+                          cz = wrap_axis(c.cz - h, d.Lz);
+                L.store[pid] = (uint8_t)d.species[((cz * d.Ly + cy) * d.Lx + cx) * d.A + c.b];
+            }
+        } else {
+            const uint32_t nw = (d.Npad + 7) / 8;
+            for (uint32_t wI = threadIdx.x; wI < nw; wI += nthreads) {
+                uint32_t word = 0;
+                for (int s = 0; s < 8; ++s) {
+                    const uint32_t pid = wI * 8 + s;
+                    if (pid >= d.Npad) break;
+                    const SiteCoord c = site_coord(pid, d.lgA, d.PX, d.PY, inv_PX, inv_PY);
+                    const int cx = wrap_axis(c.cx - h, d.Lx), cy = wrap_axis(c.cy - h, d.Ly),
+                              cz = wrap_axis(c.cz - h, d.Lz);
+                    word |= ((uint32_t)d.species[((cz * d.Ly + cy) * d.Lx + cx) * d.A + c.b] & 0xFu)
+                            << (4 * s);
+                }
+                reinterpret_cast<uint32_t *>(L.store)[wI] = word;
+            }
+        }
+    }
+    __syncthreads();
+
+    // chain counters: identical copies in every thread
+    int64_t trials = st->trials, commits = st->commits, step = st->steps;
+    int64_t nulls = st->null_trials;
+    int depth = st->depth;
+    int stop_reason = 0;
+    bool done = false;
+    const uint32_t key0 = (uint32_t)d.seed, key1 = (uint32_t)(d.seed >> 32);
+    const int h = d.halo;
+    const int zs = d.zstart[k], ze = d.zstart[k + 1];
+    const int G = (B + kWave - 1) / kWave;
+    if (trials >= d.n_trials) done = true;
+
+    for (int it = 0; it < max_steps && !done; ++it) {
+        const int64_t left = d.n_trials - trials;
+        const int tasks = left < B ? (int)left : B;
+
+        // ---- phase 1: draw and evaluate (slot, shell k) ----------------------------
+        {
+            const bool active = slot < tasks;
+            uint32_t p = 0, q = 0, ppos = 0, qpos = 0;
+            int a = 0, b = 0;
+            bool null_trial = true;
+            Hist cp = 0, cq = 0;
+            double dQ = 0.0;
+            if (active) {
+                uint32_t c[4] = {(uint32_t)slot, (uint32_t)step, d.chain_id, 0u};
+                philox4x32_10(c, key0, key1);
+                p = __umulhi(c[0], d.N);
+                q = __umulhi(c[1], d.N);
+                const SiteCoord sp = site_coord(p, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
+                const SiteCoord sq = site_coord(q, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
+                const int32_t pidp = padded_id(d, sp.cx + h, sp.cy + h, sp.cz + h, sp.b);
+                const int32_t pidq = padded_id(d, sq.cx + h, sq.cy + h, sq.cz + h, sq.b);
+                int bx, by, bz;
+                basis_bits(d.A, sp.b, bx, by, bz);
+                ppos = pack_pos(2 * sp.cx + bx, 2 * sp.cy + by, 2 * sp.cz + bz);
+                basis_bits(d.A, sq.b, bx, by, bz);
+                qpos = pack_pos(2 * sq.cx + bx, 2 * sq.cy + by, 2 * sq.cz + bz);
+                a = load_species<kStore>(L, d, pidp);
+                b = load_species<kStore>(L, d, pidq);
+                null_trial = (a == b);
+                if (!null_trial) {
+                    const int32_t *dp = L.dlin + sp.b * kMaxOffsets;
+                    const int32_t *dq = L.dlin + sq.b * kMaxOffsets;
+                    for (int t = zs; t < ze; ++t) {
+                        cp += one_at<Hist>(load_species<kStore>(L, d, pidp + dp[t]));
+                        cq += one_at<Hist>(load_species<kStore>(L, d, pidq + dq[t]));
+                    }
+                    // remove the partner: q is reached from p along m shell-k offsets
+                    int m;
+                    if (!d.small_cell) {
+                        m = min_image_r2(d, ppos, qpos) == d.r2[k] ? 1 : 0;
+                    } else {
+                        const int32_t md = mod_delta(d, ppos, qpos);
+                        m = 0;
+                        for (int t = zs; t < ze; ++t) m += (L.offmod[t] == md) ? 1 : 0;
+                    }
+                    cp -= (Hist)m << (5 * b);
+                    cq -= (Hist)m << (5 * a);
+                    // dQ_k = sum over (i, j) row-major of sq(N + dN) - sq(N)
+                    const int Da = fld(cq, a) - fld(cp, a);
+                    const int Db = fld(cq, b) - fld(cp, b);
+                    const int base = k * M * M;
+                    for (int i = 0; i < M; ++i) {
+                        const int Di = fld(cq, i) - fld(cp, i);
+                        for (int j = 0; j < M; ++j) {
+                            const int Dj = fld(cq, j) - fld(cp, j);
+                            const int dn = swap_dn(i, j, a, b, Di, Dj, Da, Db);
+                            const int e = base + i * M + j;
+                            const double sn = sq_dev(L.cnt[e] + dn, L.Rv[e], L.tv[e]);
+                            dQ = dQ + (sn - L.sqv[e]);
+                        }
+                    }
+                }
+            }
+            if (slot < B) {
+                L.rec_cp[k * B + slot] = (uint64_t)cp;
+                L.rec_cq[k * B + slot] = (uint64_t)cq;
+                L.rec_dQ[k * B + slot] = dQ;
+                if (k == 0) {
+                    L.rec_p[slot] = p;
+                    L.rec_q[slot] = q;
+                    L.rec_pp[slot] = ppos;
+                    L.rec_pq[slot] = qpos;
+                    L.rec_ab[slot] = (uint32_t)a | ((uint32_t)b << 8) |
+                                     ((uint32_t)(active && null_trial) << 16) | ((uint32_t)active << 17);
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- phase 2: dS per slot, compaction and ranking (wave 0) -------------------
+        if (wave == 0) {
+            int n_impr = 0;
+            int step_nulls = 0;
+            for (int g = 0; g < G; ++g) {
+                const int s = g * kWave + lane;
+                bool imp = false;
+                if (s < B) {
+                    const uint32_t ab = L.rec_ab[s];
+                    const bool act = (ab >> 17) & 1u, nul = (ab >> 16) & 1u;
+                    double dS = 0.0;
+                    for (int kk = 0; kk < S; ++kk) dS = dS + d.w[kk] * L.rec_dQ[kk * B + s];
+                    L.rec_dS[s] = dS;
+                    imp = act && !nul && (dS < -d.tau);
+                    step_nulls += (int)__popcll(ballot64(act && nul));
+                } else {
+                    step_nulls += (int)__popcll(ballot64(false));
+                }
+                const uint64_t mask = ballot64(imp);
+                const int before = (int)__popcll(mask & ((1ull << lane) - 1ull));
+                if (imp) L.list[n_impr + before] = s;
+                n_impr += (int)__popcll(mask);
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_s_waitcnt(0);
+            for (int idx = lane; idx < n_impr; idx += kWave) {
+                const int s = L.list[idx];
+                const double ds = L.rec_dS[s];
+                int rank = 0;
+                for (int j = 0; j < n_impr; ++j) {
+                    const int s2 = L.list[j];
+                    const double d2 = L.rec_dS[s2];
+                    rank += (d2 < ds || (d2 == ds && s2 < s)) ? 1 : 0;
+                }
+                L.order[rank] = s;
+            }
+            if (lane == 0) L.sh_int[0] = n_impr;
+            nulls += step_nulls;  // only thread 0's copy is stored
+        }
+        __syncthreads();
+
+        // ---- phase 3: commits (all waves in lock step) -------------------------------
+        const int n_impr = L.sh_int[0];
+        int n_commit = 0;
+        for (int u = 0; u < n_impr; ++u) {
+            if (d.mode == PYHEA_MODE_BEST && n_commit > 0) break;
+            const int s = L.order[u];
+            const uint32_t upp = L.rec_pp[s], upq = L.rec_pq[s];
+            bool conflict = false;
+            for (int c0 = 0; c0 < 2 * n_commit; c0 += kWave) {
+                const int c = c0 + lane;
+                bool hit = false;
+                if (c < 2 * n_commit) {
+                    const uint32_t v = L.cpos[c];
+                    hit = near_or_equal(d, upp, v) || near_or_equal(d, upq, v);
+                }
+                conflict |= ballot64(hit) != 0;
+            }
+            if (conflict) continue;
+            const uint32_t ab = L.rec_ab[s];
+            const int a = (int)(ab & 0xFFu), b = (int)((ab >> 8) & 0xFFu);
+            // this wave's shell-k change of entry e = lane (waves 0..S-1 only)
+            int dn = 0;
+            int e = 0;
+            if (wave < S && lane < M * M) {
+                const Hist cp = (Hist)L.rec_cp[k * B + s], cq = (Hist)L.rec_cq[k * B + s];
+                const int i = lane / M, j = lane % M;
+                dn = swap_dn(i, j, a, b, fld(cq, i) - fld(cp, i), fld(cq, j) - fld(cp, j),
+                             fld(cq, a) - fld(cp, a), fld(cq, b) - fld(cp, b));
+                e = k * M * M + lane;
+            }
+            bool ok = true;
+            if (n_commit > 0) {
+                if (wave < S) {
+                    double delta = 0.0;
+                    if (dn != 0) delta = sq_dev(L.cnt[e] + dn, L.Rv[e], L.tv[e]) - L.sqv[e];
+                    uint64_t mask = ballot64(dn != 0);
+                    double acc = 0.0;
+                    while (mask) {
+                        const int l = __ffsll((long long)mask) - 1;
+                        acc = acc + readlane_f64(delta, l);
+                        mask &= mask - 1;
+                    }
+                    if (lane == 0) L.sh_dQ[k] = acc;
+                }
+                __syncthreads();
+                double dS = 0.0;
+                for (int kk = 0; kk < S; ++kk) dS = dS + d.w[kk] * L.sh_dQ[kk];
+                ok = dS < -d.tau;
+                __syncthreads();
+            }
+            if (!ok) continue;
+            // apply: counts and squared deviations of shell k, species, log
+            if (wave < S && dn != 0) {
+                const int32_t n = L.cnt[e] + dn;
+                L.cnt[e] = n;
+                L.sqv[e] = sq_dev(n, L.Rv[e], L.tv[e]);
+            }
+            if (wave == 0) {
+                const uint32_t p = L.rec_p[s], q = L.rec_q[s];
+                const SiteCoord sp = site_coord(p, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
+                const SiteCoord sq = site_coord(q, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
+                write_site<kStore>(L, d, sp.cx, sp.cy, sp.cz, sp.b, b, lane);
+                write_site<kStore>(L, d, sq.cx, sq.cy, sq.cz, sq.b, a, lane);
+                if (lane == 0) {
+                    if (d.log && commits < d.log_cap) {
+                        uint32_t *rec = d.log + 4 * commits;
+                        rec[0] = (uint32_t)step;
+                        rec[1] = (uint32_t)s;
+                        rec[2] = p;
+                        rec[3] = q;
+                    }
+                    L.cpos[2 * n_commit] = upp;
+                    L.cpos[2 * n_commit + 1] = upq;
+                }
+            }
+            ++n_commit;
+            ++commits;
+            __syncthreads();
+        }
+
+        // ---- phase 4: bookkeeping --------------------------------------------------
+        trials += tasks;
+        ++step;
+        depth = n_commit > 0 ? 0 : depth + 1;
+        if (d.depth_limit > 0 && depth >= d.depth_limit) {
+            stop_reason = PYHEA_STOP_DEPTH;
+            done = true;
+        } else if (trials >= d.n_trials) {
+            stop_reason = PYHEA_STOP_TRIALS;
+            done = true;
+        }
+        __syncthreads();
+    }
+
+    // ---- write back -------------------------------------------------------------------
+    for (int e = threadIdx.x; e < E; e += nthreads) d.counts[e] = L.cnt[e];
+    if constexpr (kStore != kStoreGlobal) {
+        for (uint32_t p = threadIdx.x; p < d.N; p += nthreads) {
+            const SiteCoord c = site_coord(p, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
+            d.species[p] = (int8_t)load_species<kStore>(L, d, padded_id(d, c.cx + h, c.cy + h, c.cz + h, c.b));
+        }
+    }
+    if (threadIdx.x == 0) {
+        st->trials = trials;
+        st->commits = commits;
+        st->steps = step;
+        st->null_trials = nulls;
+        st->depth = depth;
+        if (done) {
+            st->stop_reason = stop_reason;
+            st->done = 1;
+        }
+    }
+}
+
+// padded HBM copy <-> unpadded configuration (HBM-resident chains)
+__global__ void pad_fill_kernel(const ChainDesc *__restrict__ descs) {
+    const ChainDesc &d = descs[blockIdx.y];
+    if (d.store != kStoreGlobal) return;
+    const double inv_PX = 1.0 / (double)d.PX, inv_PY = 1.0 / (double)d.PY;
+    for (uint32_t pid = blockIdx.x * blockDim.x + threadIdx.x; pid < d.Npad;
+         pid += gridDim.x * blockDim.x) {
+        const SiteCoord c = site_coord(pid, d.lgA, d.PX, d.PY, inv_PX, inv_PY);
+        const int cx = wrap_axis(c.cx - d.halo, d.Lx), cy = wrap_axis(c.cy - d.halo, d.Ly),
+                  cz = wrap_axis(c.cz - d.halo, d.Lz);
+        d.pad_global[pid] = d.species[((cz * d.Ly + cy) * d.Lx + cx) * d.A + c.b];
+    }
+}
+
+__global__ void pad_drain_kernel(const ChainDesc *__restrict__ descs) {
+    const ChainDesc &d = descs[blockIdx.y];
+    if (d.store != kStoreGlobal) return;
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < d.N; p += gridDim.x * blockDim.x) {
+        const SiteCoord c = site_coord(p, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
+        d.species[p] = d.pad_global[padded_id(d, c.cx + d.halo, c.cy + d.halo, c.cz + d.halo, c.b)];
+    }
+}
+
+}  // namespace
+
+int mc_block_threads(int S, int B) { return ((B + kWave - 1) / kWave) * S * kWave; }
+
+hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, bool wide, int S, int B,
+                     int lds_bytes, int max_steps, hipStream_t stream) {
+    const dim3 grid(n_chains), block(mc_block_threads(S, B));
+    const void *fn = nullptr;
+    if (store == kStoreLds8)
+        fn = wide ? (const void *)mc_kernel<kStoreLds8, true> : (const void *)mc_kernel<kStoreLds8, false>;
+    else if (store == kStoreLds4)
+        fn = wide ? (const void *)mc_kernel<kStoreLds4, true> : (const void *)mc_kernel<kStoreLds4, false>;
+    else
+        fn = wide ? (const void *)mc_kernel<kStoreGlobal, true> : (const void *)mc_kernel<kStoreGlobal, false>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
+    void *args[] = {(void *)&descs_dev, (void *)&max_steps};
+    return hipLaunchKernel(fn, grid, block, args, (size_t)lds_bytes, stream);
+}
+
+hipError_t launch_pad_fill(const ChainDesc *descs_dev, int n_chains, hipStream_t stream) {
+    hipLaunchKernelGGL(pad_fill_kernel, dim3(64, n_chains), dim3(256), 0, stream, descs_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_drain(const ChainDesc *descs_dev, int n_chains, hipStream_t stream) {
+    hipLaunchKernelGGL(pad_drain_kernel, dim3(64, n_chains), dim3(256), 0, stream, descs_dev);
+    return hipGetLastError();
+}
+
+}  // namespace pyhea

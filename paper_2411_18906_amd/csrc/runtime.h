@@ -1,0 +1,59 @@
+// Host runtime shared by the C ABI entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "geometry.h"
+#include "mc_kernels.h"
+
+namespace pyhea {
+
+void set_error(const std::string &msg);
+pyhea_status device_error(hipError_t e, const char *what);
+
+#define PYHEA_HIP(expr)                                       \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return device_error(_e, #expr); \
+    } while (0)
+
+// Largest dynamic LDS one workgroup may allocate on the current device.
+int max_lds_per_block();
+
+// Checks target/weight of an objective (host pointers).
+pyhea_status check_objective(const Geometry &g, const pyhea_objective *obj);
+
+// Checks MC parameters.
+pyhea_status check_params(const pyhea_mc_params *p);
+
+// Host evaluation of Eq. 2-3 from exact counts (int64 [S][M][M]).
+// n[i] = row sum of shell 1 / z_1.  Returns false if some n_i == 0.
+bool species_totals(const Geometry &g, const int64_t *counts, int64_t *n);
+void ratio_table(const Geometry &g, const int64_t *n, double *R);
+void host_objective(const Geometry &g, const int64_t *counts, const double *target,
+                    const double *weight, double *alpha, double *S_F);
+
+// One chain prepared for the MC kernel.
+struct ChainJob {
+    Geometry g;
+    pyhea_mc_params params;
+    std::vector<double> target, weight;
+    int8_t *species_dev = nullptr;  // unpadded configuration (in/out)
+    uint32_t *log_dev = nullptr;
+    int64_t log_cap = 0;
+};
+
+// Runs a set of chains to completion on `stream` (synchronous).  Groups chains
+// by launch shape; every chain's trajectory is independent of the grouping.
+// `variant` < 0 lets the autotuner choose the launch shape.
+pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
+                        std::vector<std::vector<int64_t>> *final_counts, hipStream_t stream,
+                        int variant);
+
+// Pick the species store for a chain given the LDS budget.
+int choose_store(const Geometry &g, int B, int lds_budget, int *lds_bytes);
+
+}  // namespace pyhea

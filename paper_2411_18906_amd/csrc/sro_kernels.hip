@@ -1,0 +1,295 @@
+// Full SRO evaluation kernels (Sec. 4.3, Eq. 2; Sec. 4.4, Eq. 3), the
+// per-swap evaluation API (Sec. 4.5, Eq. 4) and a device Philox stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "device_common.h"
+#include "mc_kernels.h"
+
+namespace pyhea {
+
+void fill_eval_desc(const Geometry &g, EvalDesc *d) {
+    std::memset(d, 0, sizeof(*d));
+    d->A = g.A;
+    d->lgA = g.lgA;
+    d->Lx = g.L[0];
+    d->Ly = g.L[1];
+    d->Lz = g.L[2];
+    d->M = g.M;
+    d->S = g.S;
+    d->z0 = g.z[0];
+    for (int k = 0; k < kMaxShells; ++k) d->zk[k] = k < g.S ? g.z[k] : 0;
+    d->inv_Lx = 1.0 / (double)g.L[0];
+    d->inv_Ly = 1.0 / (double)g.L[1];
+    d->N = (uint32_t)g.N;
+    d->Z = g.Z;
+    int nh = 0;
+    for (int t = 0; t < g.Z; ++t) {
+        int shell = 0;
+        while (t >= g.zstart[shell + 1]) ++shell;
+        const int dx = g.off[t][0], dy = g.off[t][1], dz = g.off[t][2];
+        d->off[t][0] = (int8_t)dx;
+        d->off[t][1] = (int8_t)dy;
+        d->off[t][2] = (int8_t)dz;
+        d->off[t][3] = (int8_t)shell;
+        // keep one offset of each +-d pair
+        const bool keep = dz > 0 || (dz == 0 && (dy > 0 || (dy == 0 && dx > 0)));
+        if (!keep) continue;
+        for (int b = 0; b < g.A; ++b) {
+            int dc[3], bt;
+            offset_target(g, b, t, dc, &bt);
+            d->half[b][nh][0] = (int8_t)dc[0];
+            d->half[b][nh][1] = (int8_t)dc[1];
+            d->half[b][nh][2] = (int8_t)dc[2];
+            d->half[b][nh][3] = (int8_t)bt;
+            d->half[b][nh][4] = (int8_t)shell;
+        }
+        ++nh;
+    }
+    d->n_half = nh;
+}
+
+namespace {
+
+__device__ __forceinline__ int wrap1(int v, int L) {
+    while (v < 0) v += L;
+    while (v >= L) v -= L;
+    return v;
+}
+
+// Pair counts by gather: every site visits one offset of each +-d pair,
+// N[k][i][j] = H[k][i][j] + H[k][j][i] with H the half counts (the map
+// p -> p - d is a bijection of the periodic cell).  LDS-privatised int32
+// histogram per workgroup, merged into global counts with one atomic per bin.
+__global__ void __launch_bounds__(256) count_gather_kernel(EvalDesc ed, int64_t K,
+                                                           const int8_t *__restrict__ species,
+                                                           int32_t *__restrict__ counts,
+                                                           int32_t *__restrict__ bad) {
+    __shared__ int32_t hist[kMaxShells * kMaxSpecies * kMaxSpecies];
+    __shared__ int32_t bad_sh;
+    const int M = ed.M, E = ed.S * ed.M * ed.M;
+    for (int64_t kc = blockIdx.y; kc < K; kc += gridDim.y) {
+        for (int e = threadIdx.x; e < E; e += blockDim.x) hist[e] = 0;
+        if (threadIdx.x == 0) bad_sh = 0;
+        __syncthreads();
+        const int8_t *sp = species + kc * (int64_t)ed.N;
+        for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < ed.N; p += gridDim.x * blockDim.x) {
+            const int s = sp[p];
+            if (s < 0 || s >= M) {
+                bad_sh = 1;
+                continue;
+            }
+            const SiteCoord c = site_coord(p, ed.lgA, ed.Lx, ed.Ly, ed.inv_Lx, ed.inv_Ly);
+            for (int hh = 0; hh < ed.n_half; ++hh) {
+                const int8_t *o = ed.half[c.b][hh];
+                const int x = wrap1(c.cx + o[0], ed.Lx);
+                const int y = wrap1(c.cy + o[1], ed.Ly);
+                const int z = wrap1(c.cz + o[2], ed.Lz);
+                const int s2 = sp[((z * ed.Ly + y) * ed.Lx + x) * ed.A + o[3]];
+                if (s2 < 0 || s2 >= M) continue;
+                atomicAdd(&hist[(o[4] * M + s) * M + s2], 1);
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < E; e += blockDim.x) {
+            const int kk = e / (M * M), i = (e / M) % M, j = e % M;
+            const int v = hist[e] + hist[(kk * M + j) * M + i];
+            if (v) atomicAdd(&counts[kc * E + e], v);
+        }
+        if (threadIdx.x == 0 && bad_sh) atomicOr(&bad[kc], 1);
+        __syncthreads();
+    }
+}
+
+__global__ void zero_i32_kernel(int32_t *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// alpha / S / F of Eq. 2-3 per configuration (one thread per configuration),
+// binary64, no contraction: R = N / (n_i n_j z_k), alpha = 1 - N_ij R,
+// Q_k = sum (alpha - t)^2, S = sum w_k Q_k, F = sqrt(S).
+__global__ void objective_kernel(EvalDesc ed, int64_t K, const int32_t *__restrict__ counts,
+                                 const int32_t *__restrict__ bad, const double *__restrict__ target,
+                                 const double *__restrict__ weight, double *__restrict__ S_F) {
+    const int64_t kc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (kc >= K) return;
+    const int M = ed.M, E = ed.S * M * M;
+    const int32_t *c = counts + kc * E;
+    int64_t n[kMaxSpecies];
+    bool ok = bad[kc] == 0;
+    for (int i = 0; i < M; ++i) {
+        int64_t r = 0;
+        for (int j = 0; j < M; ++j) r += c[i * M + j];
+        n[i] = r / ed.z0;
+        ok = ok && n[i] > 0;
+    }
+    if (!ok) {
+        S_F[2 * kc] = __longlong_as_double(0x7ff8000000000000ll);
+        S_F[2 * kc + 1] = __longlong_as_double(0x7ff8000000000000ll);
+        return;
+    }
+    double sum = 0.0;
+    for (int k = 0; k < ed.S; ++k) {
+        double Q = 0.0;
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j) {
+                const int e = (k * M + i) * M + j;
+                const double R = (double)ed.N / (double)(n[i] * n[j] * (int64_t)ed.zk[k]);
+                const double a = 1.0 - (double)c[e] * R;
+                const double dd = a - target[e];
+                Q = Q + dd * dd;
+            }
+        sum = sum + weight[k] * Q;
+    }
+    S_F[2 * kc] = sum;
+    S_F[2 * kc + 1] = sqrt(sum);
+}
+
+// site id of position (x, y, z) in half units, wrapped into the box
+__device__ __forceinline__ int32_t site_at(const EvalDesc &ed, int x, int y, int z) {
+    x = wrap1(x, 2 * ed.Lx);
+    y = wrap1(y, 2 * ed.Ly);
+    z = wrap1(z, 2 * ed.Lz);
+    int b;
+    const int px = x & 1, py = y & 1, pz = z & 1;
+    if (ed.A == 4)
+        b = (px && py) ? 1 : (px && pz) ? 2 : (py && pz) ? 3 : 0;
+    else
+        b = px;
+    return (((z >> 1) * ed.Ly + (y >> 1)) * ed.Lx + (x >> 1)) * ed.A + b;
+}
+
+// dS and dN of given swaps against one configuration (no swap applied).
+__global__ void trial_eval_kernel(EvalDesc ed, const int8_t *__restrict__ sp,
+                                  const int32_t *__restrict__ counts, const double *__restrict__ target,
+                                  const double *__restrict__ weight, int64_t n_pairs,
+                                  const int32_t *__restrict__ pairs, double *__restrict__ dS_out,
+                                  int32_t *__restrict__ dN_out) {
+    const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (u >= n_pairs) return;
+    const int M = ed.M, E = ed.S * M * M;
+    const int32_t p = pairs[2 * u], q = pairs[2 * u + 1];
+    if (p < 0 || q < 0 || (uint32_t)p >= ed.N || (uint32_t)q >= ed.N) {
+        dS_out[u] = __longlong_as_double(0x7ff8000000000000ll);
+        return;
+    }
+    const int a = sp[p], b = sp[q];
+    int64_t n[kMaxSpecies];
+    for (int i = 0; i < M; ++i) {
+        int64_t r = 0;
+        for (int j = 0; j < M; ++j) r += counts[i * M + j];
+        n[i] = r / ed.z0;
+    }
+    int pp[3], pq[3];
+    {
+        const SiteCoord c = site_coord((uint32_t)p, ed.lgA, ed.Lx, ed.Ly, ed.inv_Lx, ed.inv_Ly);
+        int bx, by, bz;
+        basis_bits(ed.A, c.b, bx, by, bz);
+        pp[0] = 2 * c.cx + bx;
+        pp[1] = 2 * c.cy + by;
+        pp[2] = 2 * c.cz + bz;
+        const SiteCoord d = site_coord((uint32_t)q, ed.lgA, ed.Lx, ed.Ly, ed.inv_Lx, ed.inv_Ly);
+        basis_bits(ed.A, d.b, bx, by, bz);
+        pq[0] = 2 * d.cx + bx;
+        pq[1] = 2 * d.cy + by;
+        pq[2] = 2 * d.cz + bz;
+    }
+    double acc = 0.0;
+    for (int k = 0; k < ed.S; ++k) {
+        int D[kMaxSpecies];
+        for (int j = 0; j < M; ++j) D[j] = 0;
+        if (a != b) {
+            for (int t = 0; t < ed.Z; ++t) {
+                if (ed.off[t][3] != k) continue;
+                const int32_t rp = site_at(ed, pp[0] + ed.off[t][0], pp[1] + ed.off[t][1], pp[2] + ed.off[t][2]);
+                const int32_t rq = site_at(ed, pq[0] + ed.off[t][0], pq[1] + ed.off[t][1], pq[2] + ed.off[t][2]);
+                if (rp != q) D[sp[rp]] -= 1;
+                if (rq != p) D[sp[rq]] += 1;
+            }
+        }
+        double dQ = 0.0;
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j) {
+                int dn = 0;
+                if (a != b) {
+                    if (i == a) dn = j == a ? 2 * D[a] : (j == b ? D[b] - D[a] : D[j]);
+                    else if (i == b) dn = j == b ? -2 * D[b] : (j == a ? D[b] - D[a] : -D[j]);
+                    else if (j == a) dn = D[i];
+                    else if (j == b) dn = -D[i];
+                }
+                const int e = (k * M + i) * M + j;
+                if (dN_out) dN_out[u * E + e] = dn;
+                const double R = (double)ed.N / (double)(n[i] * n[j] * (int64_t)ed.zk[k]);
+                const double a0 = 1.0 - (double)counts[e] * R;
+                const double d0 = a0 - target[e];
+                const double a1 = 1.0 - (double)(counts[e] + dn) * R;
+                const double d1 = a1 - target[e];
+                dQ = dQ + (d1 * d1 - d0 * d0);
+            }
+        acc = acc + weight[k] * dQ;
+    }
+    dS_out[u] = acc;
+}
+
+__global__ void philox_kernel(const uint32_t *__restrict__ ctr, uint64_t seed, int64_t n,
+                              uint32_t *__restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c[4] = {ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    for (int w = 0; w < 4; ++w) out[4 * i + w] = c[w];
+}
+
+}  // namespace
+
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(blocks), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_gather(const EvalDesc &ed, int64_t K, const int8_t *species, int32_t *counts,
+                               int32_t *bad, hipStream_t stream) {
+    const int E = ed.S * ed.M * ed.M;
+    hipError_t e = launch_zero_i32(counts, K * E, stream);
+    if (e != hipSuccess) return e;
+    e = launch_zero_i32(bad, K, stream);
+    if (e != hipSuccess) return e;
+    const int per_cfg = (int)std::min<int64_t>(std::max<int64_t>(1, (ed.N + 2047) / 2048), 1024);
+    const int gy = (int)std::min<int64_t>(K, 65535);
+    hipLaunchKernelGGL(count_gather_kernel, dim3(per_cfg, gy), dim3(256), 0, stream, ed, K, species,
+                       counts, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_objective_epilogue(const EvalDesc &ed, int64_t K, const int32_t *counts,
+                                     const int32_t *bad, const double *target, const double *weight,
+                                     double *S_F, hipStream_t stream) {
+    const int blocks = (int)((K + 255) / 256);
+    hipLaunchKernelGGL(objective_kernel, dim3(blocks), dim3(256), 0, stream, ed, K, counts, bad, target,
+                       weight, S_F);
+    return hipGetLastError();
+}
+
+hipError_t launch_trial_eval(const EvalDesc &ed, const int8_t *species, const int32_t *counts,
+                             const double *target, const double *weight, int64_t n_pairs,
+                             const int32_t *pairs, double *dS, int32_t *dN, hipStream_t stream) {
+    if (n_pairs <= 0) return hipSuccess;
+    const int blocks = (int)((n_pairs + 127) / 128);
+    hipLaunchKernelGGL(trial_eval_kernel, dim3(blocks), dim3(128), 0, stream, ed, species, counts, target,
+                       weight, n_pairs, pairs, dS, dN);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t *ctr, uint64_t seed, int64_t n, uint32_t *out, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(philox_kernel, dim3(blocks), dim3(256), 0, stream, ctr, seed, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace pyhea
