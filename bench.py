@@ -1,0 +1,191 @@
+"""Benchmark of the SRO hot path on one MI355X.
+
+Workload (one "step" = one pass over the whole hot path):
+  * full SRO evaluation of a batch of K independent FCC 20x20x20 configurations
+    (32,000 sites, 5 species, shells 1-3) in one launch;
+  * the plain single chain of that shape: 5 equiatomic species, target alpha 0,
+    unit weights, 10^6 Philox trial swaps, B = 64, disjoint commits;
+  * the batched form: 512 chains of uneven FCC/BCC cells (250-16,000 sites,
+    3-6 species, 10^5 trials each) in one persistent launch.
+Inputs are synthetic, seeded and resident in HBM before the timed region.
+
+Prints one JSON line: value = trial swaps/s of the single chain; the full
+evaluation's GB/s (with the HBM roofline of its kernel) and the batched
+chains' trial swaps/s ride along in the same line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "MC trial swaps/sec + full-SRO eval GB/s; batched vs plain at equal SRO error"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--eval-configs", type=int, default=32768)
+    ap.add_argument("--chains", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="eval,chain,batch")
+    return ap.parse_args()
+
+
+def cpu_baseline(p, budget_s: float = 12.0):
+    """The oracle, as it stands, on one host core: trial swaps/s of the same
+    chain (first trials of the budget) and sites/s of the full evaluation."""
+    from oracle import oracle as orc
+    t0 = time.perf_counter()
+    T = 20000
+    orc.mc_run(p.lattice, p.L, p.M, p.S, p.target, p.weight, p.species, seed=p.seed,
+               chain_id=p.chain_id, n_trials=T, B=p.B)
+    dt = time.perf_counter() - t0
+    # grow the sample to about the budget
+    if dt < budget_s / 2:
+        T2 = int(T * (budget_s / 2) / max(dt, 1e-3))
+        t0 = time.perf_counter()
+        orc.mc_run(p.lattice, p.L, p.M, p.S, p.target, p.weight, p.species, seed=p.seed,
+                   chain_id=p.chain_id, n_trials=T2, B=p.B)
+        dt, T = time.perf_counter() - t0, T2
+    t0 = time.perf_counter()
+    n_eval = 0
+    while time.perf_counter() - t0 < budget_s / 4 or n_eval == 0:
+        orc.counts(p.lattice, p.L, p.M, p.S, p.species)
+        n_eval += 1
+    de = time.perf_counter() - t0
+    return {"value": T / dt, "unit": "trial swaps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {T} trials of the FCC 20^3 5-species chain (B=64); "
+                      f"{n_eval} full evaluations of one 32,000-site configuration",
+            "full_eval_sites_per_s": n_eval * p.N / de,
+            "full_eval_GBps": n_eval * p.N / de / 1e9}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+              f"(independent chains and batches shard across GPUs with no exchange).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2411_18906_amd import binding as pb
+    from paper_2411_18906_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    pb.lib()
+    legs = set(args.legs.split(","))
+    stream = torch.cuda.current_stream()
+
+    # ---- inputs, resident in HBM -------------------------------------------------
+    p = wl.config2()
+    N, M, S = p.N, p.M, p.S
+    K = args.eval_configs
+    eval_in = torch.from_numpy(wl.iid_configs(N, M, min(K, 2048), seed=2)).cuda()
+    if K > eval_in.shape[0]:  # tile seeded blocks up to K configurations, each block re-permuted
+        reps = (K + eval_in.shape[0] - 1) // eval_in.shape[0]
+        blocks = [eval_in]
+        g = torch.Generator(device="cuda").manual_seed(3)
+        for r in range(1, reps):
+            perm = torch.randperm(N, device="cuda", generator=g)
+            blocks.append(eval_in[:, perm])
+        eval_in = torch.cat(blocks)[:K].contiguous()
+    counts = torch.zeros((K, S, M, M), dtype=torch.int32, device="cuda")
+    S_F = torch.zeros((K, 2), dtype=torch.float64, device="cuda")
+    chain0 = torch.from_numpy(p.species).cuda()
+    chain = chain0.clone()
+    log = torch.zeros((p.n_trials, 4), dtype=torch.int32, device="cuda")
+    par = pb.make_params(p.seed, p.chain_id, p.n_trials, p.B)
+
+    chains = wl.config4(n_chains=args.chains)
+    bspecies0 = torch.from_numpy(np.concatenate([c.species for c in chains])).cuda()
+    bspecies = bspecies0.clone()
+    boff = np.concatenate([[0], np.cumsum([c.N for c in chains])])
+    bprobs = [(c.lattice, c.L, c.M, c.S, c.target, c.weight) for c in chains]
+    bpars = [pb.make_params(c.seed, c.chain_id, c.n_trials, c.B) for c in chains]
+    b_trials = sum(c.n_trials for c in chains)
+
+    def step(ev):
+        if "eval" in legs:
+            ev["eval0"].record(stream)
+            pb.pyhea_sro_eval_batch(p.lattice, p.L, M, S, eval_in, counts, p.target, p.weight, S_F)
+            ev["eval1"].record(stream)
+        if "chain" in legs:
+            chain.copy_(chain0)
+            ev["chain0"].record(stream)
+            st, _ = pb.pyhea_mc_run(p.lattice, p.L, M, S, p.target, p.weight, chain, par, log)
+            ev["chain1"].record(stream)
+            ev["chain_stats"] = st
+        if "batch" in legs:
+            bspecies.copy_(bspecies0)
+            ev["batch0"].record(stream)
+            ev["batch_stats"] = pb.pyhea_mc_batch(bprobs, bspecies, boff, bpars)
+            ev["batch1"].record(stream)
+
+    names = ["eval0", "eval1", "chain0", "chain1", "batch0", "batch1"]
+    for _ in range(args.warmup):
+        step({n: torch.cuda.Event(enable_timing=True) for n in names})
+    torch.cuda.synchronize()
+    evs = [{n: torch.cuda.Event(enable_timing=True) for n in names} for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    def leg_ms(a, b):
+        return [e[a].elapsed_time(e[b]) for e in evs]
+
+    out = {"metric": METRIC, "unit": "trial swaps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32 counts + f64 objective",
+           "data": "synthetic (seeded)",
+           "config": {"workload": "FCC 20x20x20 (32,000 sites), 5 species, shells 1-3, target 0, "
+                                  "unit weights; chain of 10^6 trial swaps, B=64, disjoint commits",
+                      "eval_batch": K, "batched_chains": len(chains),
+                      "parallelism": "single GPU"}}
+    if "chain" in legs:
+        ms = np.array(leg_ms("chain0", "chain1"))
+        out["value"] = p.n_trials / (ms.mean() / 1e3)
+        st = evs[-1]["chain_stats"]
+        out["chain"] = {"ms": float(ms.mean()), "trials": st["trials"], "commits": st["commits"],
+                        "final_F": st["F"], "effective_trials_per_s":
+                            (st["trials"] - st["null_trials"]) / (ms.mean() / 1e3)}
+    if "eval" in legs:
+        ms = np.array(leg_ms("eval0", "eval1"))
+        alg_bytes = K * (N + S * M * M * 4 + 16)
+        gbps = alg_bytes / (ms.mean() / 1e3) / 1e9
+        out["sro_eval"] = {"GBps": gbps, "configs_per_s": K / (ms.mean() / 1e3), "ms": float(ms.mean()),
+                           "frac_hbm": gbps / HBM_PEAK_GBPS}
+        out["roofline"] = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                           "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
+                           "kernel": "full SRO evaluation (pair counts + objective) of the batch"}
+    if "batch" in legs:
+        ms = np.array(leg_ms("batch0", "batch1"))
+        bst = evs[-1]["batch_stats"]
+        fs = np.array([s["F"] for s in bst])
+        out["batched"] = {"trials_per_s": b_trials / (ms.mean() / 1e3), "ms": float(ms.mean()),
+                          "chains": len(chains), "trials": b_trials,
+                          "mean_final_F": float(fs.mean())}
+        if "chain" in legs:
+            out["batched"]["vs_plain_chain"] = out["batched"]["trials_per_s"] / out["value"]
+    if "value" not in out:
+        out["value"] = None
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -241,3 +241,52 @@ def pyhea_tune_force(variant: int):
 
 def pyhea_tune_set_cache(path: str | None):
     _check(lib().pyhea_tune_set_cache(None if path is None else path.encode()))
+
+
+class Server:
+    """Serving handle: pyhea_serve_open / submit / poll / cancel / counters / close."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int, steps_per_round: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().pyhea_serve_open(hbm_budget_bytes, max_slots, steps_per_round, ctypes.byref(h)))
+        self.h = h
+
+    def pyhea_serve_submit(self, job_id: int, lattice: int, L, M: int, S: int, target, weight,
+                           species: np.ndarray, params: McParams):
+        lat = make_lattice(lattice, L, M, S)
+        obj = _Obj(target, weight, S, M)
+        sp = np.ascontiguousarray(species, dtype=np.int8)
+        _check(lib().pyhea_serve_submit(self.h, job_id, ctypes.byref(lat), ctypes.byref(obj.c),
+                                        ctypes.byref(params), _hptr(sp)))
+
+    def pyhea_serve_poll(self, job_id: int, N: int, blocking: bool = True):
+        """(status, final species or None, stats dict, (submit, admit, finish) ns)."""
+        out = np.zeros(N, np.int8)
+        st = McStats()
+        times = np.zeros(3, np.int64)
+        code = lib().pyhea_serve_poll(self.h, job_id, _hptr(out), ctypes.byref(st), _hptr(times),
+                                      1 if blocking else 0)
+        if code == EBUSY:
+            return code, None, None, None
+        return code, (out if code == OK else None), st.as_dict(), tuple(int(t) for t in times)
+
+    def pyhea_serve_cancel(self, job_id: int) -> int:
+        return int(lib().pyhea_serve_cancel(self.h, job_id))
+
+    def pyhea_serve_counters(self) -> dict:
+        out = np.zeros(8, np.int64)
+        _check(lib().pyhea_serve_counters(self.h, _hptr(out)))
+        keys = ["submitted", "admitted", "finished", "rejected", "resident", "queued", "rounds",
+                "bytes_resident"]
+        return dict(zip(keys, (int(v) for v in out)))
+
+    def pyhea_serve_close(self):
+        if self.h:
+            _check(lib().pyhea_serve_close(self.h))
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.pyhea_serve_close()
