@@ -235,6 +235,11 @@ pyhea_status pyhea_philox4x32_10(const uint32_t *ctr_dev, uint64_t seed, int64_t
 pyhea_status pyhea_tune_set_cache(const char *path);
 pyhea_status pyhea_tune_force(int32_t variant);
 
+/* Full-evaluation kernel: -1 = automatic (bit-sliced where it covers the
+ * geometry, else gather), 0 = gather, 1 = bit-sliced where possible.  Both
+ * give identical counts. */
+pyhea_status pyhea_tune_force_eval(int32_t kernel);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,6 +25,7 @@ EXPORTS = [
     "pyhea_trial_eval", "pyhea_mc_run", "pyhea_mc_batch", "pyhea_serve_open",
     "pyhea_serve_submit", "pyhea_serve_poll", "pyhea_serve_cancel", "pyhea_serve_counters",
     "pyhea_serve_close", "pyhea_philox4x32_10", "pyhea_tune_set_cache", "pyhea_tune_force",
+    "pyhea_tune_force_eval",
 ]
 
 
@@ -88,6 +89,7 @@ def lib():
             "pyhea_philox4x32_10": ([P, u64, i64, P, P], i32),
             "pyhea_tune_set_cache": ([ctypes.c_char_p], i32),
             "pyhea_tune_force": ([i32], i32),
+            "pyhea_tune_force_eval": ([i32], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -237,6 +239,10 @@ def pyhea_philox4x32_10(ctr, seed: int, out, stream=None):
 
 def pyhea_tune_force(variant: int):
     _check(lib().pyhea_tune_force(variant))
+
+
+def pyhea_tune_force_eval(kernel: int):
+    _check(lib().pyhea_tune_force_eval(kernel))
 
 
 def pyhea_tune_set_cache(path: str | None):

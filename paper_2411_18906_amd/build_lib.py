@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpyhea.so")
 SOURCES = ["geometry.cpp", "runtime.cpp", "autotune.cpp", "api.cpp", "serve.cpp",
-           "sro_kernels.hip", "mc_kernels.hip"]
+           "sro_kernels.hip", "sro_bits.hip", "mc_kernels.hip"]
 ARCH = os.environ.get("PYHEA_OFFLOAD_ARCH", "gfx950")
 
 

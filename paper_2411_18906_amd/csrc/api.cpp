@@ -65,9 +65,10 @@ pyhea_status pyhea_sro_eval(const pyhea_lattice *lat, const int8_t *species_dev,
     PYHEA_HIP(hipMallocAsync(&buf.ptr, E * 4 + 256, stream));
     int32_t *counts = (int32_t *)buf.ptr;
     int32_t *bad = (int32_t *)((char *)buf.ptr + ((E * 4 + 127) & ~127));
-    EvalDesc ed;
-    fill_eval_desc(g, &ed);
-    PYHEA_HIP(launch_count_gather(ed, 1, species_dev, counts, bad, stream));
+    {
+        const pyhea_status s = count_configs(g, 1, species_dev, counts, bad, stream);
+        if (s != PYHEA_OK) return s;
+    }
     std::vector<int32_t> c32(E);
     int32_t badh = 0;
     PYHEA_HIP(hipMemcpyAsync(c32.data(), counts, E * 4, hipMemcpyDeviceToHost, stream));
@@ -123,7 +124,10 @@ pyhea_status pyhea_sro_eval_batch(const pyhea_lattice *lat, int64_t n_configs, c
     double *tdev = (double *)((char *)buf.ptr + tw_off);
     EvalDesc ed;
     fill_eval_desc(g, &ed);
-    PYHEA_HIP(launch_count_gather(ed, n_configs, species_dev, counts_dev, bad, stream));
+    {
+        const pyhea_status s = count_configs(g, n_configs, species_dev, counts_dev, bad, stream);
+        if (s != PYHEA_OK) return s;
+    }
     if (obj) {
         std::vector<double> tw(E + kMaxShells, 0.0);
         std::memcpy(tw.data(), obj->target, E * 8);
@@ -268,6 +272,15 @@ pyhea_status pyhea_philox4x32_10(const uint32_t *ctr_dev, uint64_t seed, int64_t
 
 pyhea_status pyhea_tune_set_cache(const char *path) {
     set_tune_cache_path(path);
+    return guard(PYHEA_OK);
+}
+
+pyhea_status pyhea_tune_force_eval(int32_t kernel) {
+    if (kernel < -1 || kernel > 1) {
+        set_error("kernel must be -1 (automatic), 0 (gather) or 1 (bit-sliced)");
+        return PYHEA_EINVAL;
+    }
+    set_forced_eval_kernel(kernel);
     return guard(PYHEA_OK);
 }
 

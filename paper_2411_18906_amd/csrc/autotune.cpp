@@ -11,6 +11,7 @@ namespace pyhea {
 namespace {
 std::mutex g_mu;
 int g_forced = -1;
+int g_forced_eval = -1;
 std::string g_cache;
 }  // namespace
 
@@ -37,6 +38,16 @@ int forced_variant() {
 void set_forced_variant(int v) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_forced = v;
+}
+
+int forced_eval_kernel() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_forced_eval;
+}
+
+void set_forced_eval_kernel(int v) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_forced_eval = v;
 }
 
 const char *tune_cache_path() {

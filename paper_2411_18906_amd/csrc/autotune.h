@@ -17,6 +17,10 @@ int tune_store_override(int variant, int default_store, const Geometry &g, int B
 // Variant forced through pyhea_tune_force (-1 = none).
 int forced_variant();
 void set_forced_variant(int v);
+// Full-evaluation kernel forced through pyhea_tune_force_eval (-1 = automatic,
+// 0 = gather, 1 = bit-sliced).
+int forced_eval_kernel();
+void set_forced_eval_kernel(int v);
 const char *tune_cache_path();
 void set_tune_cache_path(const char *p);
 

@@ -10,6 +10,7 @@
 #include <tuple>
 
 #include "autotune.h"
+#include "sro_bits.h"
 
 namespace pyhea {
 
@@ -127,6 +128,25 @@ void host_objective(const Geometry &g, const int64_t *counts, const double *targ
     }
 }
 
+pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, int32_t *counts,
+                           int32_t *bad, hipStream_t stream) {
+    if (K <= 0) return PYHEA_OK;
+    const int forced = forced_eval_kernel();
+    BitDesc bd;
+    if (forced != 0 && fill_bit_desc(g, max_lds_per_block(), K, &bd)) {
+        void *partial = nullptr;
+        PYHEA_HIP(hipMallocAsync(&partial, (size_t)K * bd.partial_stride * 4, stream));
+        const hipError_t e = launch_count_bits(g, bd, K, species, (int32_t *)partial, counts, bad, stream);
+        (void)hipFreeAsync(partial, stream);
+        PYHEA_HIP(e);
+        return PYHEA_OK;
+    }
+    EvalDesc ed;
+    fill_eval_desc(g, &ed);
+    PYHEA_HIP(launch_count_gather(ed, K, species, counts, bad, stream));
+    return PYHEA_OK;
+}
+
 int choose_store(const Geometry &g, int B, int lds_budget, int *lds_bytes) {
     const int fixed = mc_lds_bytes(g.S, g.M, B);
     const int64_t b8 = fixed + species_store_bytes(kStoreLds8, g.Npad);
@@ -200,8 +220,9 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
     std::vector<EvalDesc> eds(n);
     for (int c = 0; c < n; ++c) {
         fill_eval_desc(jobs[c].g, &eds[c]);
-        PYHEA_HIP(launch_count_gather(eds[c], 1, jobs[c].species_dev, (int32_t *)(base + slot[c].counts),
-                                      (int32_t *)(base + slot[c].bad), stream));
+        const pyhea_status s = count_configs(jobs[c].g, 1, jobs[c].species_dev, (int32_t *)(base + slot[c].counts),
+                                             (int32_t *)(base + slot[c].bad), stream);
+        if (s != PYHEA_OK) return s;
     }
     std::vector<std::vector<int32_t>> cnt32(n);
     std::vector<int32_t> bad(n);
@@ -291,9 +312,11 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
     }
 
     // results: states, maintained counts, and a fresh recount of the final configuration
-    for (int c = 0; c < n; ++c)
-        PYHEA_HIP(launch_count_gather(eds[c], 1, jobs[c].species_dev, (int32_t *)(base + slot[c].recount),
-                                      (int32_t *)(base + slot[c].bad), stream));
+    for (int c = 0; c < n; ++c) {
+        const pyhea_status s = count_configs(jobs[c].g, 1, jobs[c].species_dev, (int32_t *)(base + slot[c].recount),
+                                             (int32_t *)(base + slot[c].bad), stream);
+        if (s != PYHEA_OK) return s;
+    }
     std::vector<ChainState> sts(n);
     std::vector<std::vector<int32_t>> rec32(n);
     for (int c = 0; c < n; ++c) {

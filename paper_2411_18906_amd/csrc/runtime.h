@@ -53,6 +53,11 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
                         std::vector<std::vector<int64_t>> *final_counts, hipStream_t stream,
                         int variant);
 
+// Pair counts of K configurations of one geometry (counts [K][S][M][M], bad [K]):
+// the bit-sliced kernel when it covers the geometry, else the gather kernel.
+pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, int32_t *counts,
+                           int32_t *bad, hipStream_t stream);
+
 // Pick the species store for a chain given the LDS budget.
 int choose_store(const Geometry &g, int B, int lds_budget, int *lds_bytes);
 

@@ -134,10 +134,8 @@ bool Server::admit(Job *j, hipStream_t s) {
     ok = ok && hipMemcpyAsync(base + j->off_R, R.data(), E * 8, hipMemcpyHostToDevice, s) == hipSuccess;
     ok = ok && hipMemcpyAsync(base + j->off_t, j->target.data(), E * 8, hipMemcpyHostToDevice, s) == hipSuccess;
     ok = ok && hipMemcpyAsync(base + j->off_state, &st0, sizeof(st0), hipMemcpyHostToDevice, s) == hipSuccess;
-    EvalDesc ed;
-    fill_eval_desc(g, &ed);
-    ok = ok && launch_count_gather(ed, 1, (const int8_t *)(base + j->off_species), (int32_t *)(base + j->off_counts),
-                                   (int32_t *)(base + j->off_bad), s) == hipSuccess;
+    ok = ok && count_configs(g, 1, (const int8_t *)(base + j->off_species), (int32_t *)(base + j->off_counts),
+                             (int32_t *)(base + j->off_bad), s) == PYHEA_OK;
     ChainDesc &d = j->desc;
     std::memset(&d, 0, sizeof(d));
     fill_chain_geometry(g, &d);
@@ -185,10 +183,8 @@ void Server::retire(Job *j, hipStream_t s) {
         ok = ok && hipStreamSynchronize(s) == hipSuccess;
         if (tmp) (void)hipFree(tmp);
     }
-    EvalDesc ed;
-    fill_eval_desc(g, &ed);
-    ok = ok && launch_count_gather(ed, 1, (const int8_t *)(base + j->off_species), (int32_t *)(base + j->off_recount),
-                                   (int32_t *)(base + j->off_bad), s) == hipSuccess;
+    ok = ok && count_configs(g, 1, (const int8_t *)(base + j->off_species), (int32_t *)(base + j->off_recount),
+                             (int32_t *)(base + j->off_bad), s) == PYHEA_OK;
     ChainState st;
     std::vector<int32_t> cm(E), cr(E);
     ok = ok && hipMemcpyAsync(&st, base + j->off_state, sizeof(st), hipMemcpyDeviceToHost, s) == hipSuccess;

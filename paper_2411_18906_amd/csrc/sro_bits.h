@@ -1,0 +1,39 @@
+// Bit-sliced full evaluation (FCC): descriptor and launcher.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "geometry.h"
+
+namespace pyhea {
+
+struct BitDesc {
+    int32_t Lx, Ly, Lz;
+    int32_t RS;        // flat row stride in bits (Lx + 2)
+    int32_t LW;        // words per plane (flat (Ly + 2) * RS bits)
+    int32_t PADW;      // zero words before and after each plane
+    int32_t PW;        // LW + 2 * PADW
+    int32_t cw0, NCW;  // words that hold centre sites
+    int32_t nchx;      // 32-cell chunks per row
+    int32_t ZC;        // centre layers per workgroup
+    int32_t nchunks;   // workgroups per configuration
+    int32_t partial_stride;
+    uint32_t N;
+    int32_t nh;
+    int32_t hstart[kMaxShells + 1];
+    int32_t zk[kMaxShells];
+    int32_t tab_delta[4][kMaxOffsets / 2];  // neighbour plane word offset per (basis, half offset)
+    int32_t tab_r[4][kMaxOffsets / 2];      // funnel-shift amount
+};
+
+// Fills bd; false if the bit-sliced kernel does not cover this geometry.
+// K is the number of configurations of the launch: few configurations are
+// split along z over more workgroups.
+bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, BitDesc *bd);
+
+// counts [K][S][M][M] and bad [K] of K configurations; `partial` is scratch of
+// K * bd.partial_stride int32.
+hipError_t launch_count_bits(const Geometry &g, const BitDesc &bd, int64_t K, const int8_t *species,
+                             int32_t *partial, int32_t *counts, int32_t *bad, hipStream_t stream);
+
+}  // namespace pyhea

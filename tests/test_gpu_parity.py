@@ -83,9 +83,25 @@ def test_sro_eval_rejects_bad_species():
         pb.pyhea_sro_eval(lattice, L, M, S, dev(sp))
 
 
-@pytest.mark.parametrize("lattice,L,M,S,K", [(orc.FCC, (5, 5, 5), 5, 3, 40), (orc.BCC, (6, 4, 5), 4, 2, 33),
-                                             (orc.FCC, (20, 20, 20), 5, 3, 3)])
-def test_sro_eval_batch_matches_oracle(lattice, L, M, S, K):
+BATCH_SHAPES = [
+    (orc.FCC, (5, 5, 5), 5, 3, 40), (orc.BCC, (6, 4, 5), 4, 2, 33), (orc.FCC, (20, 20, 20), 5, 3, 3),
+    (orc.FCC, (40, 40, 40), 4, 2, 3), (orc.FCC, (33, 5, 7), 3, 4, 4), (orc.FCC, (1, 2, 3), 2, 1, 5),
+    (orc.FCC, (70, 3, 6), 6, 2, 4), (orc.FCC, (2, 2, 2), 8, 2, 6), (orc.FCC, (7, 3, 2), 7, 1, 5),
+    (orc.FCC, (6, 5, 4), 6, 4, 5), (orc.FCC, (64, 64, 64), 5, 3, 3),
+]
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("lattice,L,M,S,K", BATCH_SHAPES)
+def test_sro_eval_batch_matches_oracle(lattice, L, M, S, K, kernel):
+    pb.pyhea_tune_force_eval(kernel)
+    try:
+        _batch_case(lattice, L, M, S, K)
+    finally:
+        pb.pyhea_tune_force_eval(-1)
+
+
+def _batch_case(lattice, L, M, S, K):
     N = orc.n_sites(lattice, L)
     cfg = wl.iid_configs(N, M, K, seed=K)
     cfg[1, :] = 0                      # species missing -> NaN
@@ -100,7 +116,7 @@ def test_sro_eval_batch_matches_oracle(lattice, L, M, S, K):
     c = counts.cpu().numpy()
     sf = SF.cpu().numpy()
     for k in range(K):
-        if k in (1, 2):
+        if k in (1, 2) or (np.bincount(cfg[k], minlength=M) == 0).any():
             assert np.all(np.isnan(sf[k]))
             continue
         want = orc.counts(lattice, L, M, S, cfg[k])
