@@ -17,6 +17,7 @@ struct BitDesc {
     int32_t nchx;      // 32-cell chunks per row
     int32_t ZC;        // centre layers per workgroup
     int32_t nchunks;   // workgroups per configuration
+    int32_t threads;   // workgroup size
     int32_t partial_stride;
     uint32_t N;
     int32_t nh;

@@ -29,7 +29,7 @@ namespace pyhea {
 
 namespace {
 
-constexpr int kThreads = 512;
+constexpr int kMaxThreads = 1024;
 
 template <int M>
 struct Pairs {
@@ -65,7 +65,7 @@ __device__ __forceinline__ int wave_sum(int v) {
 __device__ __forceinline__ int qdiv(int n, double inv) { return (int)div_small((uint32_t)n, inv); }
 
 template <int M, int S>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
 count_bits_kernel(BitDesc bd, int64_t K,
                                                                const int8_t *__restrict__ species,
                                                                int32_t *__restrict__ partial) {
@@ -339,7 +339,7 @@ hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_
     }
     for (int64_t k0 = 0; k0 < K; k0 += 65535) {
         const int64_t kn = std::min<int64_t>(65535, K - k0);
-        hipLaunchKernelGGL((count_bits_kernel<M, S>), dim3(bd.nchunks, (unsigned)kn), dim3(kThreads), lds, stream,
+        hipLaunchKernelGGL((count_bits_kernel<M, S>), dim3(bd.nchunks, (unsigned)kn), dim3(bd.threads), lds, stream,
                            bd, kn, species + k0 * (int64_t)bd.N, partial + k0 * bd.partial_stride);
     }
     hipLaunchKernelGGL((finalize_bits_kernel<M, S>), dim3((unsigned)((K + 127) / 128)), dim3(128), 0, stream, bd, K,
@@ -400,9 +400,6 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, BitDesc *bd) {
     const int per_layer = 4 * P * bd->PW * 4;
     int zc = (lds_budget - fixed) / per_layer - 1;
     if (zc < 1) return false;
-    // prefer chunks small enough for two workgroups per CU, split evenly
-    const int zc2 = (lds_budget / 2 - fixed) / per_layer - 1;
-    if (zc2 >= 4) zc = zc2;
     zc = std::min(zc, g.L[2]);
     zc = (g.L[2] + (g.L[2] + zc - 1) / zc - 1) / ((g.L[2] + zc - 1) / zc);
     // few configurations: spread each over up to 512 / K workgroups along z
@@ -410,6 +407,7 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, BitDesc *bd) {
     if (want > 1) zc = std::min<int64_t>(zc, std::max<int64_t>(2, (g.L[2] + want - 1) / want));
     bd->ZC = zc;
     bd->nchunks = (g.L[2] + zc - 1) / zc;
+    bd->threads = 512;
     // half offsets ordered by shell
     int nh = 0;
     for (int k = 0; k < g.S; ++k) {
