@@ -30,7 +30,8 @@
  *    binary64 with no fused multiply-add:
  *        R     = (double)N_sites / (double)(n_i * n_j * z_k)
  *        alpha = 1 - N[k][i][j] * R           (P_ij = N_ij/(n_i z_k), c_j = n_j/N)
- *        Q_k   = sum_{i,j row-major} (alpha - target)^2,   S = sum_k w_k Q_k,
+ *        Q_k   = sum_i (sum_j (alpha - target)^2),   S = sum_k w_k Q_k,
+ *        (each sum from +0.0 in increasing index order)
  *        F     = sqrt(S)                      (Eq. 3: F is the fitness)
  *  - Limits: M in [2, 8]; S in [1, 4]; N_sites * max z_k < 2^31; no shell
  *    offset may map a site onto itself (PYHEA_EINVAL otherwise).

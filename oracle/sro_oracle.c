@@ -223,8 +223,9 @@ void or_species_counts(int64_t N, int M, const int8_t *species, int64_t *n_out) 
  * alpha_ij = 1 - P_ij / c_j = 1 - N_ij * N / (n_i n_j z_k).  The factor
  * R = N / (n_i n_j z_k) is one IEEE division of two exact integers; then
  * alpha = 1 - N_ij * R and d = alpha - target.  Eq. 3 is evaluated with its own
- * nesting: Q_k = sum over (i, j) row-major of d * d (from +0.0), then
- * S = sum over k of w_k * Q_k (from +0.0), F = sqrt(S).
+ * nesting: for each row i the sum over j of d * d (from +0.0), Q_k = the sum of
+ * the row sums over i (from +0.0), then S = sum over k of w_k * Q_k (from
+ * +0.0), F = sqrt(S).
  */
 void or_ratio_table(int64_t N, int M, int S, const int *z, const int64_t *n, double *R) {
     for (int k = 0; k < S; ++k)
@@ -256,15 +257,18 @@ void or_alpha_objective(int lattice, const int *L, int M, int S, const int8_t *s
     double sum = 0.0;
     for (int k = 0; k < S; ++k) {
         double Q = 0.0;
-        for (int i = 0; i < M; ++i)
+        for (int i = 0; i < M; ++i) {
+            double row = 0.0;
             for (int j = 0; j < M; ++j) {
                 int e = (k * M + i) * M + j;
                 double a = 1.0 - (double)counts[e] * R[e];
                 double d = a - target[e];
                 if (alpha) alpha[e] = a;
                 if (sq) sq[e] = d * d;
-                Q = Q + d * d;
+                row = row + d * d;
             }
+            Q = Q + row;
+        }
         sum = sum + weight[k] * Q;
     }
     S_F[0] = sum;
@@ -313,21 +317,24 @@ void or_swap_delta(int lattice, const int *L, int M, int S, const int8_t *specie
     }
 }
 
-/* dS = sum over k of w_k * dQ_k (from +0.0), where dQ_k is the sum over (i, j)
- * row-major of sq(N + dN) - sq(N) (from +0.0).  Entries with dN = 0 add
- * exactly +0.0. */
+/* dS = sum over k of w_k * dQ_k (from +0.0), with the nesting of Eq. 3:
+ * dQ_k = sum over i of (sum over j of sq(N + dN) - sq(N)), each sum from +0.0.
+ * Entries with dN = 0 add exactly +0.0. */
 static double delta_objective(int M, int S, const int64_t *counts, const int64_t *dN,
                               const double *R, const double *target, const double *weight,
                               const double *sq) {
     double acc = 0.0;
     for (int k = 0; k < S; ++k) {
         double dQ = 0.0;
-        for (int i = 0; i < M; ++i)
+        for (int i = 0; i < M; ++i) {
+            double row = 0.0;
             for (int j = 0; j < M; ++j) {
                 int e = (k * M + i) * M + j;
                 double sn = sq_dev(counts[e] + dN[e], R[e], target[e]);
-                dQ = dQ + (sn - sq[e]);
+                row = row + (sn - sq[e]);
             }
+            dQ = dQ + row;
+        }
         acc = acc + weight[k] * dQ;
     }
     return acc;

@@ -12,8 +12,8 @@ __host__ __device__ inline int mc_lds_bytes(int S, int M, int B) {
     auto r = [](int b) { return (b + 15) & ~15; };
     const int E = S * M * M;
     int n = 0;
-    n += r(E * 4) + 3 * r(E * 8);                 // cnt, sqv, Rv, tv
-    n += r(4 * kMaxOffsets * 4) + r(kMaxOffsets * 4);  // dlin, offmod
+    n += r(E * 32);                               // entry records
+    n += r(kMaxOffsets * 16) + r(kMaxOffsets * 4);     // dlin4, offmod
     n += r(B * 8) + 5 * r(B * 4);                 // rec_dS, p, q, pp, pq, ab
     n += 3 * r(S * B * 8);                        // rec_cp, rec_cq, rec_dQ
     n += 2 * r(B * 4) + r(2 * B * 4);             // order, list, cpos
@@ -29,7 +29,7 @@ inline int64_t species_store_bytes(int store, int64_t Npad) {
 }
 
 int mc_block_threads(int S, int B);
-hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, bool wide, int S, int B,
+hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M, int S, int B,
                      int lds_bytes, int max_steps, hipStream_t stream);
 hipError_t launch_pad_fill(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);
 hipError_t launch_pad_drain(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);

@@ -11,7 +11,7 @@
 //     (slot, step, chain, 0)), gathers the species of the z_k shell-k
 //     neighbours of both sites from the halo-padded configuration (one linear
 //     delta per (basis, offset), no modulo), removes the partner site, and
-//     forms D = c_q - c_p and dQ_k = sum_{i,j} sq(N + dN) - sq(N) (Eq. 4-5);
+//     forms D = c_q - c_p and dQ_k = sum_i sum_j sq(N + dN) - sq(N) (Eq. 4-5);
 //  2. wave 0 sums dS = sum_k w_k dQ_k per slot, compacts the improving slots
 //     (dS < -tau) and ranks them by (dS, slot) (Eq. 6);
 //  3. all waves walk the ranking in lock step: BEST stops after one commit;
@@ -47,29 +47,25 @@ __device__ __forceinline__ H one_at(int j) {
     return (H)1 << (5 * j);
 }
 
-// dN[i][j] of swapping species a (at p) and b (at q), a != b (Eq. 4 in count
-// form): rows/columns a and b change by +-D, the diagonal by 2D, (a,b) by
-// D[b] - D[a]; all other entries are unchanged.
-__device__ __forceinline__ int swap_dn(int i, int j, int a, int b, int Di, int Dj, int Da, int Db) {
-    if (i == a) return j == a ? 2 * Da : (j == b ? Db - Da : Dj);
-    if (i == b) return j == b ? -2 * Db : (j == a ? Db - Da : -Dj);
-    if (j == a) return Di;
-    if (j == b) return -Di;
-    return 0;
-}
-
 __device__ __forceinline__ double sq_dev(int32_t n, double R, double t) {
     const double alpha = 1.0 - (double)n * R;
     const double d = alpha - t;
     return d * d;
 }
 
+// One (k, i, j) entry: the ratio R = N/(n_i n_j z_k), the target, the cached
+// squared deviation and the exact pair count, read together (two 16-byte loads).
+struct Ent {
+    double R;
+    double t;
+    double sq;
+    int32_t cnt;
+    int32_t pad;
+};
+
 struct Lds {
-    int32_t *cnt;   // [S][M][M]
-    double *sqv;    // [S][M][M]
-    double *Rv;     // [S][M][M]
-    double *tv;     // [S][M][M]
-    int32_t *dlin;  // [4][kMaxOffsets]
+    Ent *ent;       // [S][M][M]
+    int4 *dlin4;    // [kMaxOffsets]: linear deltas of offset t from bases 0..3
     int32_t *offmod;
     double *rec_dS;     // [B]
     uint32_t *rec_p;    // [B]
@@ -172,31 +168,32 @@ __device__ __forceinline__ bool near_or_equal(const ChainDesc &d, uint32_t u, ui
     return hit;
 }
 
-// write species v at site (cx, cy, cz, b) and at every halo copy of it
+// write species v at site (cx, cy, cz, b) and at every halo copy of it: padded
+// coordinates x0 + i*Lx < PX per axis (at most 5 per axis), one lane per copy
 template <int kStore>
 __device__ void write_site(const Lds &L, const ChainDesc &d, int cx, int cy, int cz, int b, int v,
                            int lane) {
     const int h = d.halo;
     const int x0 = wrap_axis(cx + h, d.Lx), y0 = wrap_axis(cy + h, d.Ly), z0 = wrap_axis(cz + h, d.Lz);
-    const int nx = (d.PX - 1 - x0) / d.Lx + 1;
-    const int ny = (d.PY - 1 - y0) / d.Ly + 1;
-    const int nz = (d.PZ - 1 - z0) / d.Lz + 1;
-    const int total = nx * ny * nz;
-    for (int t = lane; t < total; t += kWave) {
-        const int ix = t % nx, iy = (t / nx) % ny, iz = t / (nx * ny);
-        store_species<kStore>(L, d, padded_id(d, x0 + ix * d.Lx, y0 + iy * d.Ly, z0 + iz * d.Lz, b), v);
+    for (int t = lane; t < 512; t += kWave) {
+        const int px = x0 + (t & 7) * d.Lx, py = y0 + ((t >> 3) & 7) * d.Ly, pz = z0 + (t >> 6) * d.Lz;
+        if (px < d.PX && py < d.PY && pz < d.PZ) store_species<kStore>(L, d, padded_id(d, px, py, pz, b), v);
     }
 }
 
-template <int kStore, bool kWide>
+__device__ __forceinline__ int sel4(int4 v, int b) {
+    return b == 0 ? v.x : (b == 1 ? v.y : (b == 2 ? v.z : v.w));
+}
+
+template <int kStore, int M>
 __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ descs,
                                                   int32_t max_steps) {
-    using Hist = typename HistT<kWide>::type;
+    using Hist = typename HistT<(M > 6)>::type;
     const ChainDesc &d = descs[blockIdx.x];
     ChainState *st = d.state;
     if (st->done) return;
 
-    const int S = d.S, M = d.M, E = S * M * M;
+    const int S = d.S, E = S * M * M;
     const int B = d.B;
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
@@ -209,11 +206,8 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
     Lds L;
     {
         uint8_t *p = smem;
-        L.cnt = (int32_t *)carve(p, E * 4);
-        L.sqv = (double *)carve(p, E * 8);
-        L.Rv = (double *)carve(p, E * 8);
-        L.tv = (double *)carve(p, E * 8);
-        L.dlin = (int32_t *)carve(p, 4 * kMaxOffsets * 4);
+        L.ent = (Ent *)carve(p, E * sizeof(Ent));
+        L.dlin4 = (int4 *)carve(p, kMaxOffsets * 16);
         L.offmod = (int32_t *)carve(p, kMaxOffsets * 4);
         L.rec_dS = (double *)carve(p, B * 8);
         L.rec_p = (uint32_t *)carve(p, B * 4);
@@ -234,12 +228,16 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
 
     // ---- load chain state into LDS ------------------------------------------------
     for (int e = threadIdx.x; e < E; e += nthreads) {
-        L.cnt[e] = d.counts[e];
-        L.Rv[e] = d.R[e];
-        L.tv[e] = d.target[e];
-        L.sqv[e] = sq_dev(L.cnt[e], L.Rv[e], L.tv[e]);
+        Ent en;
+        en.cnt = d.counts[e];
+        en.R = d.R[e];
+        en.t = d.target[e];
+        en.sq = sq_dev(en.cnt, en.R, en.t);
+        en.pad = 0;
+        L.ent[e] = en;
     }
-    for (int t = threadIdx.x; t < 4 * kMaxOffsets; t += nthreads) L.dlin[t] = d.dlin[t / kMaxOffsets][t % kMaxOffsets];
+    for (int t = threadIdx.x; t < kMaxOffsets; t += nthreads)
+        L.dlin4[t] = make_int4(d.dlin[0][t], d.dlin[1][t], d.dlin[2][t], d.dlin[3][t]);
     for (int t = threadIdx.x; t < kMaxOffsets; t += nthreads) L.offmod[t] = d.off_mod[t];
     if constexpr (kStore != kStoreGlobal) {
         // fill the halo-padded configuration from the unpadded one
@@ -313,11 +311,37 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                 b = load_species<kStore>(L, d, pidq);
                 null_trial = (a == b);
                 if (!null_trial) {
-                    const int32_t *dp = L.dlin + sp.b * kMaxOffsets;
-                    const int32_t *dq = L.dlin + sq.b * kMaxOffsets;
-                    for (int t = zs; t < ze; ++t) {
-                        cp += one_at<Hist>(load_species<kStore>(L, d, pidp + dp[t]));
-                        cq += one_at<Hist>(load_species<kStore>(L, d, pidq + dq[t]));
+                    // neighbour species, 6 offsets at a time: all loads issued before use
+                    constexpr int kU = 6;
+                    int t = zs;
+#pragma unroll 1
+                    for (; t + kU <= ze; t += kU) {
+                        int4 dl[kU];
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) dl[u] = L.dlin4[t + u];
+                        int ap[kU], aq[kU];
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            ap[u] = pidp + sel4(dl[u], sp.b);
+                            aq[u] = pidq + sel4(dl[u], sq.b);
+                        }
+                        int vp[kU], vq[kU];
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            vp[u] = load_species<kStore>(L, d, ap[u]);
+                            vq[u] = load_species<kStore>(L, d, aq[u]);
+                        }
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            cp += one_at<Hist>(vp[u]);
+                            cq += one_at<Hist>(vq[u]);
+                        }
+                    }
+#pragma unroll 1
+                    for (; t < ze; ++t) {
+                        const int4 dl = L.dlin4[t];
+                        cp += one_at<Hist>(load_species<kStore>(L, d, pidp + sel4(dl, sp.b)));
+                        cq += one_at<Hist>(load_species<kStore>(L, d, pidq + sel4(dl, sq.b)));
                     }
                     // remove the partner: q is reached from p along m shell-k offsets
                     int m;
@@ -330,19 +354,26 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                     }
                     cp -= (Hist)m << (5 * b);
                     cq -= (Hist)m << (5 * a);
-                    // dQ_k = sum over (i, j) row-major of sq(N + dN) - sq(N)
-                    const int Da = fld(cq, a) - fld(cp, a);
-                    const int Db = fld(cq, b) - fld(cp, b);
-                    const int base = k * M * M;
+                    // D = c_q - c_p and u = +1 at species a, -1 at b: dN[i][j] = u_i D_j + u_j D_i
+                    int D[M], u[M];
+#pragma unroll
+                    for (int j = 0; j < M; ++j) {
+                        D[j] = fld(cq, j) - fld(cp, j);
+                        u[j] = (j == a ? 1 : 0) - (j == b ? 1 : 0);
+                    }
+                    // dQ_k = sum over rows i of (sum over j of sq(N + dN) - sq(N))
+                    const Ent *row = L.ent + k * M * M;
+#pragma unroll
                     for (int i = 0; i < M; ++i) {
-                        const int Di = fld(cq, i) - fld(cp, i);
+                        double rs = 0.0;
+#pragma unroll
                         for (int j = 0; j < M; ++j) {
-                            const int Dj = fld(cq, j) - fld(cp, j);
-                            const int dn = swap_dn(i, j, a, b, Di, Dj, Da, Db);
-                            const int e = base + i * M + j;
-                            const double sn = sq_dev(L.cnt[e] + dn, L.Rv[e], L.tv[e]);
-                            dQ = dQ + (sn - L.sqv[e]);
+                            const Ent en = row[i * M + j];
+                            const int dn = __mul24(u[i], D[j]) + __mul24(u[j], D[i]);
+                            const double sn = sq_dev(en.cnt + dn, en.R, en.t);
+                            rs = rs + (sn - en.sq);
                         }
+                        dQ = dQ + rs;
                     }
                 }
             }
@@ -428,23 +459,35 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
             int e = 0;
             if (wave < S && lane < M * M) {
                 const Hist cp = (Hist)L.rec_cp[k * B + s], cq = (Hist)L.rec_cq[k * B + s];
-                const int i = lane / M, j = lane % M;
-                dn = swap_dn(i, j, a, b, fld(cq, i) - fld(cp, i), fld(cq, j) - fld(cp, j),
-                             fld(cq, a) - fld(cp, a), fld(cq, b) - fld(cp, b));
+                const int i = lane / M, j = lane - (lane / M) * M;
+                const int ui = (i == a ? 1 : 0) - (i == b ? 1 : 0), uj = (j == a ? 1 : 0) - (j == b ? 1 : 0);
+                dn = __mul24(ui, fld(cq, j) - fld(cp, j)) + __mul24(uj, fld(cq, i) - fld(cp, i));
                 e = k * M * M + lane;
             }
             bool ok = true;
             if (n_commit > 0) {
                 if (wave < S) {
                     double delta = 0.0;
-                    if (dn != 0) delta = sq_dev(L.cnt[e] + dn, L.Rv[e], L.tv[e]) - L.sqv[e];
+                    if (dn != 0) {
+                        const Ent en = L.ent[e];
+                        delta = sq_dev(en.cnt + dn, en.R, en.t) - en.sq;
+                    }
+                    // row sums, then their sum (entries with dN = 0 add exactly +0.0)
                     uint64_t mask = ballot64(dn != 0);
-                    double acc = 0.0;
+                    double acc = 0.0, rs = 0.0;
+                    int cur = -1;
                     while (mask) {
                         const int l = __ffsll((long long)mask) - 1;
-                        acc = acc + readlane_f64(delta, l);
+                        const int r = l / M;
+                        if (r != cur) {
+                            acc = acc + rs;
+                            rs = 0.0;
+                            cur = r;
+                        }
+                        rs = rs + readlane_f64(delta, l);
                         mask &= mask - 1;
                     }
+                    acc = acc + rs;
                     if (lane == 0) L.sh_dQ[k] = acc;
                 }
                 __syncthreads();
@@ -456,9 +499,10 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
             if (!ok) continue;
             // apply: counts and squared deviations of shell k, species, log
             if (wave < S && dn != 0) {
-                const int32_t n = L.cnt[e] + dn;
-                L.cnt[e] = n;
-                L.sqv[e] = sq_dev(n, L.Rv[e], L.tv[e]);
+                Ent en = L.ent[e];
+                en.cnt += dn;
+                en.sq = sq_dev(en.cnt, en.R, en.t);
+                L.ent[e] = en;
             }
             if (wave == 0) {
                 const uint32_t p = L.rec_p[s], q = L.rec_q[s];
@@ -498,7 +542,7 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
     }
 
     // ---- write back -------------------------------------------------------------------
-    for (int e = threadIdx.x; e < E; e += nthreads) d.counts[e] = L.cnt[e];
+    for (int e = threadIdx.x; e < E; e += nthreads) d.counts[e] = L.ent[e].cnt;
     if constexpr (kStore != kStoreGlobal) {
         for (uint32_t p = threadIdx.x; p < d.N; p += nthreads) {
             const SiteCoord c = site_coord(p, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
@@ -545,16 +589,25 @@ __global__ void pad_drain_kernel(const ChainDesc *__restrict__ descs) {
 
 int mc_block_threads(int S, int B) { return ((B + kWave - 1) / kWave) * S * kWave; }
 
-hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, bool wide, int S, int B,
+template <int kStore>
+const void *mc_fn(int M) {
+    switch (M) {
+        case 2: return (const void *)mc_kernel<kStore, 2>;
+        case 3: return (const void *)mc_kernel<kStore, 3>;
+        case 4: return (const void *)mc_kernel<kStore, 4>;
+        case 5: return (const void *)mc_kernel<kStore, 5>;
+        case 6: return (const void *)mc_kernel<kStore, 6>;
+        case 7: return (const void *)mc_kernel<kStore, 7>;
+        default: return (const void *)mc_kernel<kStore, 8>;
+    }
+}
+
+hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M, int S, int B,
                      int lds_bytes, int max_steps, hipStream_t stream) {
     const dim3 grid(n_chains), block(mc_block_threads(S, B));
-    const void *fn = nullptr;
-    if (store == kStoreLds8)
-        fn = wide ? (const void *)mc_kernel<kStoreLds8, true> : (const void *)mc_kernel<kStoreLds8, false>;
-    else if (store == kStoreLds4)
-        fn = wide ? (const void *)mc_kernel<kStoreLds4, true> : (const void *)mc_kernel<kStoreLds4, false>;
-    else
-        fn = wide ? (const void *)mc_kernel<kStoreGlobal, true> : (const void *)mc_kernel<kStoreGlobal, false>;
+    const void *fn = store == kStoreLds8 ? mc_fn<kStoreLds8>(M)
+                     : store == kStoreLds4 ? mc_fn<kStoreLds4>(M)
+                                           : mc_fn<kStoreGlobal>(M);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
     void *args[] = {(void *)&descs_dev, (void *)&max_steps};

@@ -110,16 +110,19 @@ void host_objective(const Geometry &g, const int64_t *counts, const double *targ
     double sum = 0.0;
     for (int k = 0; k < g.S; ++k) {
         double Q = 0.0;
-        for (int i = 0; i < g.M; ++i)
+        for (int i = 0; i < g.M; ++i) {
+            double row = 0.0;
             for (int j = 0; j < g.M; ++j) {
                 const int e = (k * g.M + i) * g.M + j;
                 const double a = 1.0 - (double)counts[e] * R[e];
                 if (alpha) alpha[e] = a;
                 if (target) {
                     const double d = a - target[e];
-                    Q = Q + d * d;
+                    row = row + d * d;
                 }
             }
+            Q = Q + row;
+        }
         if (weight) sum = sum + weight[k] * Q;
     }
     if (S_F) {
@@ -282,7 +285,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         d.state = (ChainState *)(base + slot[c].state);
         d.store = slot[c].store;
         d.lds_bytes = slot[c].lds;
-        groups[{slot[c].store, j.g.M > 6 ? 1 : 0, j.g.S, d.B}].push_back(c);
+        groups[{slot[c].store, j.g.M, j.g.S, d.B}].push_back(c);
     }
     DeviceBuffer dbuf;
     PYHEA_HIP(hipMalloc(&dbuf.ptr, sizeof(ChainDesc) * n));
@@ -307,7 +310,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         int lds = 0;
         for (int c : L.second) lds = std::max(lds, descs[c].lds_bytes);
         if (d0.store == kStoreGlobal) PYHEA_HIP(launch_pad_fill(ddev + first, count, stream));
-        PYHEA_HIP(launch_mc(ddev + first, count, d0.store, d0.M > 6, d0.S, d0.B, lds, INT_MAX, stream));
+        PYHEA_HIP(launch_mc(ddev + first, count, d0.store, d0.M, d0.S, d0.B, lds, INT_MAX, stream));
         if (d0.store == kStoreGlobal) PYHEA_HIP(launch_pad_drain(ddev + first, count, stream));
     }
 

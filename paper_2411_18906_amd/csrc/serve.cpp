@@ -279,7 +279,7 @@ void Server::run() {
         // one round: group by launch shape, one stream per group
         std::map<std::tuple<int, int, int, int>, std::vector<Job *>> groups;
         for (Job *j : run_set)
-            groups[{j->store, j->g.M > 6 ? 1 : 0, j->g.S, j->params.cand_per_step}].push_back(j);
+            groups[{j->store, j->g.M, j->g.S, j->params.cand_per_step}].push_back(j);
         std::vector<ChainDesc> descs;
         std::vector<std::pair<size_t, std::vector<Job *>>> launches;
         for (auto &kv : groups) {
@@ -295,7 +295,7 @@ void Server::run() {
             int lds = 0;
             for (Job *j : L.second) lds = std::max(lds, j->lds);
             hipStream_t s = streams[gi % streams.size()];
-            ok = launch_mc((const ChainDesc *)desc_dev + L.first, (int)L.second.size(), j0->store, j0->g.M > 6,
+            ok = launch_mc((const ChainDesc *)desc_dev + L.first, (int)L.second.size(), j0->store, j0->g.M,
                            j0->g.S, j0->params.cand_per_step, lds, steps_per_round, s) == hipSuccess;
         }
         for (hipStream_t s : streams) ok = ok && hipStreamSynchronize(s) == hipSuccess;

@@ -110,7 +110,7 @@ __global__ void zero_i32_kernel(int32_t *p, int64_t n) {
 
 // alpha / S / F of Eq. 2-3 per configuration (one thread per configuration),
 // binary64, no contraction: R = N / (n_i n_j z_k), alpha = 1 - N_ij R,
-// Q_k = sum (alpha - t)^2, S = sum w_k Q_k, F = sqrt(S).
+// Q_k = sum_i (sum_j (alpha - t)^2), S = sum_k w_k Q_k, F = sqrt(S).
 __global__ void objective_kernel(EvalDesc ed, int64_t K, const int32_t *__restrict__ counts,
                                  const int32_t *__restrict__ bad, const double *__restrict__ target,
                                  const double *__restrict__ weight, double *__restrict__ S_F) {
@@ -134,14 +134,17 @@ __global__ void objective_kernel(EvalDesc ed, int64_t K, const int32_t *__restri
     double sum = 0.0;
     for (int k = 0; k < ed.S; ++k) {
         double Q = 0.0;
-        for (int i = 0; i < M; ++i)
+        for (int i = 0; i < M; ++i) {
+            double row = 0.0;
             for (int j = 0; j < M; ++j) {
                 const int e = (k * M + i) * M + j;
                 const double R = (double)ed.N / (double)(n[i] * n[j] * (int64_t)ed.zk[k]);
                 const double a = 1.0 - (double)c[e] * R;
                 const double dd = a - target[e];
-                Q = Q + dd * dd;
+                row = row + dd * dd;
             }
+            Q = Q + row;
+        }
         sum = sum + weight[k] * Q;
     }
     S_F[2 * kc] = sum;
@@ -211,7 +214,8 @@ __global__ void trial_eval_kernel(EvalDesc ed, const int8_t *__restrict__ sp,
             }
         }
         double dQ = 0.0;
-        for (int i = 0; i < M; ++i)
+        for (int i = 0; i < M; ++i) {
+            double rowsum = 0.0;
             for (int j = 0; j < M; ++j) {
                 int dn = 0;
                 if (a != b) {
@@ -227,8 +231,10 @@ __global__ void trial_eval_kernel(EvalDesc ed, const int8_t *__restrict__ sp,
                 const double d0 = a0 - target[e];
                 const double a1 = 1.0 - (double)(counts[e] + dn) * R;
                 const double d1 = a1 - target[e];
-                dQ = dQ + (d1 * d1 - d0 * d0);
+                rowsum = rowsum + (d1 * d1 - d0 * d0);
             }
+            dQ = dQ + rowsum;
+        }
         acc = acc + weight[k] * dQ;
     }
     dS_out[u] = acc;
