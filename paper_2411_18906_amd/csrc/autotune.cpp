@@ -15,19 +15,28 @@ int g_forced_eval = -1;
 std::string g_cache;
 }  // namespace
 
-int tune_store_override(int variant, int default_store, const Geometry &g, int B, int lds_budget,
-                        int *lds_bytes) {
-    const int fixed = mc_lds_bytes(g.S, g.M, B);
-    const int64_t b4 = fixed + species_store_bytes(kStoreLds4, g.Npad);
-    if (variant == 1 && b4 <= lds_budget) {
-        *lds_bytes = (int)b4;
-        return kStoreLds4;
+LaunchShape choose_launch(const Geometry &g, int B, int lds_budget, int variant) {
+    LaunchShape ls;
+    const int fixed1 = mc_lds_bytes(g.S, g.M, B, 1);
+    const int64_t b8 = fixed1 + species_store_bytes(kStoreLds8, g.Npad);
+    const int64_t b4 = fixed1 + species_store_bytes(kStoreLds4, g.Npad);
+    if (variant == 2) {
+        ls.store = kStoreGlobal;
+    } else if (variant == 1) {
+        ls.store = b4 <= lds_budget ? kStoreLds4 : kStoreGlobal;
+    } else {
+        ls.store = b8 <= lds_budget ? kStoreLds8 : (b4 <= lds_budget ? kStoreLds4 : kStoreGlobal);
     }
-    if (variant == 1 || variant == 2) {
-        *lds_bytes = fixed;
-        return kStoreGlobal;
+    ls.H = 1;
+    ls.lds = (int)(fixed1 + species_store_bytes(ls.store, g.Npad));
+    if (variant != 3 && mc_halves(g.S, B) == 2) {
+        const int64_t l2 = mc_lds_bytes(g.S, g.M, B, 2) + species_store_bytes(ls.store, g.Npad);
+        if (l2 <= lds_budget) {
+            ls.H = 2;
+            ls.lds = (int)l2;
+        }
     }
-    return default_store;
+    return ls;
 }
 
 int forced_variant() {

@@ -7,12 +7,21 @@
 
 namespace pyhea {
 
-// Variants: 0 = LDS bytes when they fit, else LDS nibbles, else HBM (default);
-// 1 = LDS nibbles when they fit, else HBM; 2 = always HBM.
-constexpr int kNumStoreVariants = 3;
+// Launch shape of one chain: where its configuration lives (LDS bytes, LDS
+// nibbles or HBM) and how many wavefronts share each shell (H = 1 or 2).
+struct LaunchShape {
+    int store;
+    int H;
+    int lds;
+};
 
-int tune_store_override(int variant, int default_store, const Geometry &g, int B, int lds_budget,
-                        int *lds_bytes);
+// Variants: 0 = automatic (LDS bytes when they fit, else nibbles, else HBM;
+// two wavefronts per shell when the block and LDS allow); 1 = LDS nibbles when
+// they fit, else HBM; 2 = always HBM; 3 = automatic store, one wavefront per
+// shell.  Every variant gives bit-identical results.
+constexpr int kNumStoreVariants = 4;
+
+LaunchShape choose_launch(const Geometry &g, int B, int lds_budget, int variant);
 
 // Variant forced through pyhea_tune_force (-1 = none).
 int forced_variant();

@@ -8,7 +8,7 @@
 namespace pyhea {
 
 // LDS layout of the MC kernel (must match the carve order in mc_kernels.hip).
-__host__ __device__ inline int mc_lds_bytes(int S, int M, int B) {
+__host__ __device__ inline int mc_lds_bytes(int S, int M, int B, int H = 1) {
     auto r = [](int b) { return (b + 15) & ~15; };
     const int E = S * M * M;
     int n = 0;
@@ -18,6 +18,7 @@ __host__ __device__ inline int mc_lds_bytes(int S, int M, int B) {
     n += 3 * r(S * B * 8);                        // rec_cp, rec_cq, rec_dQ
     n += 2 * r(B * 4) + r(2 * B * 4);             // order, list, cpos
     n += r(kMaxShells * 8) + r(16 * 4);           // sh_dQ, sh_int
+    if (H == 2) n += r(2 * 2 * S * B * 8) + r(S * B * 4 * 8);  // partial histograms, row sums
     return n;
 }
 
@@ -28,8 +29,11 @@ inline int64_t species_store_bytes(int store, int64_t Npad) {
     return 0;
 }
 
-int mc_block_threads(int S, int B);
-hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M, int S, int B,
+int mc_block_threads(int S, int B, int H);
+
+// Halves per shell: 2 when the block stays within 1024 threads.
+inline int mc_halves(int S, int B) { return ((B + 63) / 64) * S * 2 <= 16 ? 2 : 1; }
+hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M, int S, int B, int H,
                      int lds_bytes, int max_steps, hipStream_t stream);
 hipError_t launch_pad_fill(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);
 hipError_t launch_pad_drain(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);

@@ -81,6 +81,8 @@ struct Lds {
     uint32_t *cpos;     // [2B] committed site positions
     double *sh_dQ;      // [kMaxShells]
     int32_t *sh_int;    // scalars
+    uint64_t *part;     // [S][2 halves][2 (cp, cq)][B] partial histograms (H == 2)
+    double *rowbuf;     // [S][B][4] row sums of the second half (H == 2)
     uint8_t *store;     // species store
 };
 
@@ -187,7 +189,7 @@ __device__ __forceinline__ int sel4(int4 v, int b) {
 
 template <int kStore, int M>
 __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ descs,
-                                                  int32_t max_steps) {
+                                                  int32_t max_steps, int32_t H) {
     using Hist = typename HistT<(M > 6)>::type;
     const ChainDesc &d = descs[blockIdx.x];
     ChainState *st = d.state;
@@ -197,9 +199,11 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
     const int B = d.B;
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    const int k = wave % S;     // shell handled by this wave
-    const int grp = wave / S;   // slot group
+    const int hh = wave % H;          // half of the shell's work (H = 1 or 2)
+    const int k = (wave / H) % S;     // shell handled by this wave
+    const int grp = wave / (S * H);   // slot group
     const int slot = grp * kWave + lane;
+    const bool lead = hh == 0;        // the wave that owns the slot's records
     const int nthreads = blockDim.x;
 
     extern __shared__ __align__(16) uint8_t smem[];
@@ -223,6 +227,10 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
         L.cpos = (uint32_t *)carve(p, 2 * B * 4);
         L.sh_dQ = (double *)carve(p, kMaxShells * 8);
         L.sh_int = (int32_t *)carve(p, 16 * 4);
+        if (H == 2) {
+            L.part = (uint64_t *)carve(p, 2 * 2 * S * B * 8);
+            L.rowbuf = (double *)carve(p, S * B * 4 * 8);
+        }
         L.store = p;
     }
 
@@ -277,7 +285,14 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
     bool done = false;
     const uint32_t key0 = (uint32_t)d.seed, key1 = (uint32_t)(d.seed >> 32);
     const int h = d.halo;
-    const int zs = d.zstart[k], ze = d.zstart[k + 1];
+    // this wave's offsets and rows of shell k
+    const int zsk = d.zstart[k], zek = d.zstart[k + 1];
+    const int zmid = zsk + (zek - zsk) / 2;
+    const int zs = H == 2 ? (lead ? zsk : zmid) : zsk;
+    const int ze = H == 2 ? (lead ? zmid : zek) : zek;
+    constexpr int RH = M / 2;
+    const int r0 = H == 2 ? (lead ? 0 : RH) : 0;
+    const int r1 = H == 2 ? (lead ? RH : M) : M;
     const int G = (B + kWave - 1) / kWave;
     if (trials >= d.n_trials) done = true;
 
@@ -290,7 +305,7 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
             const bool active = slot < tasks;
             uint32_t p = 0, q = 0, ppos = 0, qpos = 0;
             int a = 0, b = 0;
-            bool null_trial = true;
+            bool live = false;
             Hist cp = 0, cq = 0;
             double dQ = 0.0;
             if (active) {
@@ -309,8 +324,8 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                 qpos = pack_pos(2 * sq.cx + bx, 2 * sq.cy + by, 2 * sq.cz + bz);
                 a = load_species<kStore>(L, d, pidp);
                 b = load_species<kStore>(L, d, pidq);
-                null_trial = (a == b);
-                if (!null_trial) {
+                live = (a != b);
+                if (live) {
                     // neighbour species, 6 offsets at a time: all loads issued before use
                     constexpr int kU = 6;
                     int t = zs;
@@ -343,41 +358,69 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                         cp += one_at<Hist>(load_species<kStore>(L, d, pidp + sel4(dl, sp.b)));
                         cq += one_at<Hist>(load_species<kStore>(L, d, pidq + sel4(dl, sq.b)));
                     }
-                    // remove the partner: q is reached from p along m shell-k offsets
-                    int m;
-                    if (!d.small_cell) {
-                        m = min_image_r2(d, ppos, qpos) == d.r2[k] ? 1 : 0;
-                    } else {
-                        const int32_t md = mod_delta(d, ppos, qpos);
-                        m = 0;
-                        for (int t = zs; t < ze; ++t) m += (L.offmod[t] == md) ? 1 : 0;
-                    }
-                    cp -= (Hist)m << (5 * b);
-                    cq -= (Hist)m << (5 * a);
-                    // D = c_q - c_p and u = +1 at species a, -1 at b: dN[i][j] = u_i D_j + u_j D_i
-                    int D[M], u[M];
-#pragma unroll
-                    for (int j = 0; j < M; ++j) {
-                        D[j] = fld(cq, j) - fld(cp, j);
-                        u[j] = (j == a ? 1 : 0) - (j == b ? 1 : 0);
-                    }
-                    // dQ_k = sum over rows i of (sum over j of sq(N + dN) - sq(N))
-                    const Ent *row = L.ent + k * M * M;
-#pragma unroll
-                    for (int i = 0; i < M; ++i) {
-                        double rs = 0.0;
-#pragma unroll
-                        for (int j = 0; j < M; ++j) {
-                            const Ent en = row[i * M + j];
-                            const int dn = __mul24(u[i], D[j]) + __mul24(u[j], D[i]);
-                            const double sn = sq_dev(en.cnt + dn, en.R, en.t);
-                            rs = rs + (sn - en.sq);
-                        }
-                        dQ = dQ + rs;
-                    }
                 }
             }
-            if (slot < B) {
+            if (H == 2) {
+                // exchange the two halves' partial histograms (exact integer sums)
+                uint64_t *mine = L.part + ((k * 2 + hh) * 2) * B;
+                const uint64_t *other = L.part + ((k * 2 + (1 - hh)) * 2) * B;
+                if (slot < B) {
+                    mine[slot] = (uint64_t)cp;
+                    mine[B + slot] = (uint64_t)cq;
+                }
+                __syncthreads();
+                if (live) {
+                    cp += (Hist)other[slot];
+                    cq += (Hist)other[B + slot];
+                }
+            }
+            if (live) {
+                // remove the partner: q is reached from p along m shell-k offsets
+                int m;
+                if (!d.small_cell) {
+                    m = min_image_r2(d, ppos, qpos) == d.r2[k] ? 1 : 0;
+                } else {
+                    const int32_t md = mod_delta(d, ppos, qpos);
+                    m = 0;
+                    for (int t = zsk; t < zek; ++t) m += (L.offmod[t] == md) ? 1 : 0;
+                }
+                cp -= (Hist)m << (5 * b);
+                cq -= (Hist)m << (5 * a);
+                // D = c_q - c_p and u = +1 at species a, -1 at b: dN[i][j] = u_i D_j + u_j D_i
+                int D[M], u[M];
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    D[j] = fld(cq, j) - fld(cp, j);
+                    u[j] = (j == a ? 1 : 0) - (j == b ? 1 : 0);
+                }
+                // dQ_k = sum over rows i of (sum over j of sq(N + dN) - sq(N)); this wave
+                // takes rows [r0, r1)
+                const Ent *row = L.ent + k * M * M;
+#pragma unroll
+                for (int i = 0; i < M; ++i) {
+                    if (i < r0 || i >= r1) continue;
+                    double rs = 0.0;
+#pragma unroll
+                    for (int j = 0; j < M; ++j) {
+                        const Ent en = row[i * M + j];
+                        const int dn = __mul24(u[i], D[j]) + __mul24(u[j], D[i]);
+                        const double sn = sq_dev(en.cnt + dn, en.R, en.t);
+                        rs = rs + (sn - en.sq);
+                    }
+                    if (lead)
+                        dQ = dQ + rs;
+                    else
+                        L.rowbuf[(k * B + slot) * 4 + (i - RH)] = rs;
+                }
+            }
+            if (H == 2) {
+                __syncthreads();
+                if (lead && live) {
+#pragma unroll
+                    for (int i = RH; i < M; ++i) dQ = dQ + L.rowbuf[(k * B + slot) * 4 + (i - RH)];
+                }
+            }
+            if (lead && slot < B) {
                 L.rec_cp[k * B + slot] = (uint64_t)cp;
                 L.rec_cq[k * B + slot] = (uint64_t)cq;
                 L.rec_dQ[k * B + slot] = dQ;
@@ -387,7 +430,7 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                     L.rec_pp[slot] = ppos;
                     L.rec_pq[slot] = qpos;
                     L.rec_ab[slot] = (uint32_t)a | ((uint32_t)b << 8) |
-                                     ((uint32_t)(active && null_trial) << 16) | ((uint32_t)active << 17);
+                                     ((uint32_t)(active && !live) << 16) | ((uint32_t)active << 17);
                 }
             }
         }
@@ -457,7 +500,8 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
             // this wave's shell-k change of entry e = lane (waves 0..S-1 only)
             int dn = 0;
             int e = 0;
-            if (wave < S && lane < M * M) {
+            const bool ewave = grp == 0 && lead;   // one wave per shell handles its entries
+            if (ewave && lane < M * M) {
                 const Hist cp = (Hist)L.rec_cp[k * B + s], cq = (Hist)L.rec_cq[k * B + s];
                 const int i = lane / M, j = lane - (lane / M) * M;
                 const int ui = (i == a ? 1 : 0) - (i == b ? 1 : 0), uj = (j == a ? 1 : 0) - (j == b ? 1 : 0);
@@ -466,7 +510,7 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
             }
             bool ok = true;
             if (n_commit > 0) {
-                if (wave < S) {
+                if (ewave) {
                     double delta = 0.0;
                     if (dn != 0) {
                         const Ent en = L.ent[e];
@@ -498,7 +542,7 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
             }
             if (!ok) continue;
             // apply: counts and squared deviations of shell k, species, log
-            if (wave < S && dn != 0) {
+            if (ewave && dn != 0) {
                 Ent en = L.ent[e];
                 en.cnt += dn;
                 en.sq = sq_dev(en.cnt, en.R, en.t);
@@ -587,7 +631,7 @@ __global__ void pad_drain_kernel(const ChainDesc *__restrict__ descs) {
 
 }  // namespace
 
-int mc_block_threads(int S, int B) { return ((B + kWave - 1) / kWave) * S * kWave; }
+int mc_block_threads(int S, int B, int H) { return ((B + kWave - 1) / kWave) * S * H * kWave; }
 
 template <int kStore>
 const void *mc_fn(int M) {
@@ -602,15 +646,15 @@ const void *mc_fn(int M) {
     }
 }
 
-hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M, int S, int B,
+hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M, int S, int B, int H,
                      int lds_bytes, int max_steps, hipStream_t stream) {
-    const dim3 grid(n_chains), block(mc_block_threads(S, B));
+    const dim3 grid(n_chains), block(mc_block_threads(S, B, H));
     const void *fn = store == kStoreLds8 ? mc_fn<kStoreLds8>(M)
                      : store == kStoreLds4 ? mc_fn<kStoreLds4>(M)
                                            : mc_fn<kStoreGlobal>(M);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
-    void *args[] = {(void *)&descs_dev, (void *)&max_steps};
+    void *args[] = {(void *)&descs_dev, (void *)&max_steps, (void *)&H};
     return hipLaunchKernel(fn, grid, block, args, (size_t)lds_bytes, stream);
 }
 

@@ -150,22 +150,6 @@ pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, 
     return PYHEA_OK;
 }
 
-int choose_store(const Geometry &g, int B, int lds_budget, int *lds_bytes) {
-    const int fixed = mc_lds_bytes(g.S, g.M, B);
-    const int64_t b8 = fixed + species_store_bytes(kStoreLds8, g.Npad);
-    const int64_t b4 = fixed + species_store_bytes(kStoreLds4, g.Npad);
-    if (b8 <= lds_budget) {
-        *lds_bytes = (int)b8;
-        return kStoreLds8;
-    }
-    if (b4 <= lds_budget) {
-        *lds_bytes = (int)b4;
-        return kStoreLds4;
-    }
-    *lds_bytes = fixed;
-    return kStoreGlobal;
-}
-
 namespace {
 
 struct DeviceBuffer {
@@ -189,7 +173,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
     // device arena: per chain counts, recount, bad flag, R, target, state, padded copy
     struct Slot {
         size_t counts, recount, bad, R, target, state, pad;
-        int store, lds;
+        int store, lds, H;
     };
     std::vector<Slot> slot(n);
     size_t total = 0;
@@ -209,9 +193,10 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         total = align256(total + E * 8);
         s.state = total;
         total = align256(total + sizeof(ChainState));
-        s.store = choose_store(g, jobs[c].params.cand_per_step, lds_budget, &s.lds);
-        if (variant >= 0) s.store = tune_store_override(variant, s.store, g, jobs[c].params.cand_per_step,
-                                                         lds_budget, &s.lds);
+        const LaunchShape ls = choose_launch(g, jobs[c].params.cand_per_step, lds_budget, variant < 0 ? 0 : variant);
+        s.store = ls.store;
+        s.lds = ls.lds;
+        s.H = ls.H;
         s.pad = total;
         if (s.store == kStoreGlobal) total = align256(total + (size_t)g.Npad);
     }
@@ -259,8 +244,8 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         PYHEA_HIP(hipMemcpyAsync(base + slot[c].state, &st0, sizeof(st0), hipMemcpyHostToDevice, stream));
     }
 
-    // descriptors, grouped by launch shape (store, wide, S, B)
-    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
+    // descriptors, grouped by launch shape (store, M, S, B, H)
+    std::map<std::tuple<int, int, int, int, int>, std::vector<int>> groups;
     std::vector<ChainDesc> descs(n);
     for (int c = 0; c < n; ++c) {
         const ChainJob &j = jobs[c];
@@ -285,7 +270,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         d.state = (ChainState *)(base + slot[c].state);
         d.store = slot[c].store;
         d.lds_bytes = slot[c].lds;
-        groups[{slot[c].store, j.g.M, j.g.S, d.B}].push_back(c);
+        groups[{slot[c].store, j.g.M, j.g.S, d.B, slot[c].H}].push_back(c);
     }
     DeviceBuffer dbuf;
     PYHEA_HIP(hipMalloc(&dbuf.ptr, sizeof(ChainDesc) * n));
@@ -310,7 +295,8 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         int lds = 0;
         for (int c : L.second) lds = std::max(lds, descs[c].lds_bytes);
         if (d0.store == kStoreGlobal) PYHEA_HIP(launch_pad_fill(ddev + first, count, stream));
-        PYHEA_HIP(launch_mc(ddev + first, count, d0.store, d0.M, d0.S, d0.B, lds, INT_MAX, stream));
+        PYHEA_HIP(launch_mc(ddev + first, count, d0.store, d0.M, d0.S, d0.B, slot[L.second[0]].H, lds, INT_MAX,
+                            stream));
         if (d0.store == kStoreGlobal) PYHEA_HIP(launch_pad_drain(ddev + first, count, stream));
     }
 

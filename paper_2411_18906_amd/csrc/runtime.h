@@ -58,7 +58,5 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
 pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, int32_t *counts,
                            int32_t *bad, hipStream_t stream);
 
-// Pick the species store for a chain given the LDS budget.
-int choose_store(const Geometry &g, int B, int lds_budget, int *lds_bytes);
 
 }  // namespace pyhea

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "pyhea.h"
+#include "autotune.h"
 #include "runtime.h"
 
 using namespace pyhea;
@@ -58,6 +59,7 @@ struct Job {
     ChainDesc desc{};
     int store = kStoreLds8;
     int lds = 0;
+    int H = 1;
     size_t off_counts = 0, off_recount = 0, off_bad = 0, off_R = 0, off_t = 0, off_state = 0,
            off_species = 0, off_pad = 0;
 };
@@ -277,9 +279,9 @@ void Server::run() {
             continue;
         }
         // one round: group by launch shape, one stream per group
-        std::map<std::tuple<int, int, int, int>, std::vector<Job *>> groups;
+        std::map<std::tuple<int, int, int, int, int>, std::vector<Job *>> groups;
         for (Job *j : run_set)
-            groups[{j->store, j->g.M, j->g.S, j->params.cand_per_step}].push_back(j);
+            groups[{j->store, j->g.M, j->g.S, j->params.cand_per_step, j->H}].push_back(j);
         std::vector<ChainDesc> descs;
         std::vector<std::pair<size_t, std::vector<Job *>>> launches;
         for (auto &kv : groups) {
@@ -296,7 +298,7 @@ void Server::run() {
             for (Job *j : L.second) lds = std::max(lds, j->lds);
             hipStream_t s = streams[gi % streams.size()];
             ok = launch_mc((const ChainDesc *)desc_dev + L.first, (int)L.second.size(), j0->store, j0->g.M,
-                           j0->g.S, j0->params.cand_per_step, lds, steps_per_round, s) == hipSuccess;
+                           j0->g.S, j0->params.cand_per_step, j0->H, lds, steps_per_round, s) == hipSuccess;
         }
         for (hipStream_t s : streams) ok = ok && hipStreamSynchronize(s) == hipSuccess;
         // done flags
@@ -432,7 +434,10 @@ pyhea_status pyhea_serve_submit(void *server, uint64_t job_id, const pyhea_latti
     const int E = g.S * g.M * g.M;
     j->target.assign(obj->target, obj->target + E);
     j->weight.assign(obj->weight, obj->weight + g.S);
-    j->store = choose_store(g, params->cand_per_step, s->lds_budget, &j->lds);
+    const LaunchShape ls = choose_launch(g, params->cand_per_step, s->lds_budget, 0);
+    j->store = ls.store;
+    j->lds = ls.lds;
+    j->H = ls.H;
     j->footprint = job_footprint(g, j->store);
     std::lock_guard<std::mutex> lk(s->mu);
     if (j->footprint > s->budget) {

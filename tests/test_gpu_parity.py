@@ -216,7 +216,7 @@ def test_mc_zero_and_partial_budgets():
         assert_same_chain(o, g)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_store_variants_are_bit_identical(variant):
     lattice, L, M, S = orc.FCC, (6, 6, 6), 5, 3
     rng = np.random.default_rng(5)
