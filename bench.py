@@ -71,6 +71,24 @@ def cpu_baseline(p, budget_s: float = 12.0):
             "full_eval_GBps": n_eval * p.N / de / 1e9}
 
 
+def recorded_traffic():
+    """HBM bytes per launch of the full-evaluation kernel from the committed
+    rocprofv3 counter summary, if that summary was taken on the current kernel
+    source (otherwise None)."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "full_eval_fcc20_5sp_traffic.md")
+    src = os.path.join(ROOT, "paper_2411_18906_amd", "csrc", "sro_bits.hip")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    vals = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(("traffic_bytes", "kernel_source")))
+    if vals.get("kernel_source_sha256_prefix", "").strip() != sha:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -116,7 +134,11 @@ def main():
     bpars = [pb.make_params(c.seed, c.chain_id, c.n_trials, c.B) for c in chains]
     b_trials = sum(c.n_trials for c in chains)
 
+    copy_dst = torch.empty_like(eval_in) if "copy" in legs else None
+
     def step(ev):
+        if "copy" in legs:   # plain copy of the evaluation batch: counter calibration
+            copy_dst.copy_(eval_in)
         if "eval" in legs:
             ev["eval0"].record(stream)
             pb.pyhea_sro_eval_batch(p.lattice, p.L, M, S, eval_in, counts, p.target, p.weight, S_F)
@@ -168,8 +190,10 @@ def main():
         gbps = alg_bytes / (ms.mean() / 1e3) / 1e9
         out["sro_eval"] = {"GBps": gbps, "configs_per_s": K / (ms.mean() / 1e3), "ms": float(ms.mean()),
                            "frac_hbm": gbps / HBM_PEAK_GBPS}
+        tb = recorded_traffic()
         out["roofline"] = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                           "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
+                           "frac": gbps / HBM_PEAK_GBPS,
+                           "traffic": None if tb is None else tb / (ms.mean() / 1e3) / 1e9,
                            "kernel": "full SRO evaluation (pair counts + objective) of the batch"}
     if "batch" in legs:
         ms = np.array(leg_ms("batch0", "batch1"))

@@ -124,18 +124,21 @@ pyhea_status pyhea_sro_eval_batch(const pyhea_lattice *lat, int64_t n_configs, c
     double *tdev = (double *)((char *)buf.ptr + tw_off);
     EvalDesc ed;
     fill_eval_desc(g, &ed);
-    {
-        const pyhea_status s = count_configs(g, n_configs, species_dev, counts_dev, bad, stream);
-        if (s != PYHEA_OK) return s;
-    }
+    std::vector<double> tw(E + kMaxShells, 0.0);
     if (obj) {
-        std::vector<double> tw(E + kMaxShells, 0.0);
         std::memcpy(tw.data(), obj->target, E * 8);
         std::memcpy(tw.data() + E, obj->weight, g.S * 8);
+        // from pageable memory the runtime performs this copy synchronously, so tw may go out of scope
         PYHEA_HIP(hipMemcpyAsync(tdev, tw.data(), tw.size() * 8, hipMemcpyHostToDevice, stream));
-        PYHEA_HIP(launch_objective_epilogue(ed, n_configs, counts_dev, bad, tdev, tdev + E, S_F_dev, stream));
-        PYHEA_HIP(hipStreamSynchronize(stream));  // tw is host memory
     }
+    bool fused = false;
+    {
+        const pyhea_status s = count_configs(g, n_configs, species_dev, counts_dev, bad, stream, obj ? tdev : nullptr,
+                                             obj ? S_F_dev : nullptr, &fused);
+        if (s != PYHEA_OK) return s;
+    }
+    if (obj && !fused)
+        PYHEA_HIP(launch_objective_epilogue(ed, n_configs, counts_dev, bad, tdev, tdev + E, S_F_dev, stream));
     return guard(PYHEA_OK);
 }
 

@@ -132,16 +132,20 @@ void host_objective(const Geometry &g, const int64_t *counts, const double *targ
 }
 
 pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, int32_t *counts,
-                           int32_t *bad, hipStream_t stream) {
+                           int32_t *bad, hipStream_t stream, const double *tw, double *S_F, bool *fused) {
+    if (fused) *fused = false;
     if (K <= 0) return PYHEA_OK;
     const int forced = forced_eval_kernel();
     BitDesc bd;
     if (forced != 0 && fill_bit_desc(g, max_lds_per_block(), K, &bd)) {
         void *partial = nullptr;
-        PYHEA_HIP(hipMallocAsync(&partial, (size_t)K * bd.partial_stride * 4, stream));
-        const hipError_t e = launch_count_bits(g, bd, K, species, (int32_t *)partial, counts, bad, stream);
-        (void)hipFreeAsync(partial, stream);
+        if (bd.nchunks > 1) PYHEA_HIP(hipMallocAsync(&partial, (size_t)K * bd.partial_stride * 4, stream));
+        const bool fuse = S_F && bd.nchunks == 1;
+        const hipError_t e = launch_count_bits(g, bd, K, species, (int32_t *)partial, counts, bad,
+                                               fuse ? tw : nullptr, fuse ? S_F : nullptr, stream);
+        if (partial) (void)hipFreeAsync(partial, stream);
         PYHEA_HIP(e);
+        if (fused) *fused = fuse;
         return PYHEA_OK;
     }
     EvalDesc ed;

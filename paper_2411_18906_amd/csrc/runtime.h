@@ -55,8 +55,11 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
 
 // Pair counts of K configurations of one geometry (counts [K][S][M][M], bad [K]):
 // the bit-sliced kernel when it covers the geometry, else the gather kernel.
+// With S_F (and tw = {target, weight} on the device) the objective may be
+// computed by the counting kernel itself; *fused says whether it was.
 pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, int32_t *counts,
-                           int32_t *bad, hipStream_t stream);
+                           int32_t *bad, hipStream_t stream, const double *tw = nullptr, double *S_F = nullptr,
+                           bool *fused = nullptr);
 
 
 }  // namespace pyhea

@@ -68,7 +68,11 @@ template <int M, int S>
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
 count_bits_kernel(BitDesc bd, int64_t K,
                                                                const int8_t *__restrict__ species,
-                                                               int32_t *__restrict__ partial) {
+                                                               int32_t *__restrict__ partial,
+                                                               int32_t *__restrict__ counts_out,
+                                                               int32_t *__restrict__ bad_out,
+                                                               const double *__restrict__ tw,
+                                                               double *__restrict__ S_F) {
     constexpr int P = Pairs<M>::P;
     constexpr int NP = Pairs<M>::NP;
     extern __shared__ __align__(16) uint32_t lds[];
@@ -266,14 +270,87 @@ count_bits_kernel(BitDesc bd, int64_t K,
         if ((threadIdx.x & 63) == 0 && anybad) atomicOr(&red[S * NP + P], 1);
     }
     __syncthreads();
-    int32_t *out = partial + kc * (int64_t)bd.partial_stride;
-    for (int i = threadIdx.x; i < S * NP + P + 1; i += blockDim.x) {
-        if (bd.nchunks == 1)
-            out[i] = red[i];
-        else if (i < S * NP + P)
-            atomicAdd(&out[i], red[i]);
-        else if (red[i])
-            atomicOr(&out[i], red[i]);
+    if (bd.nchunks > 1) {
+        int32_t *out = partial + kc * (int64_t)bd.partial_stride;
+        for (int i = threadIdx.x; i < S * NP + P + 1; i += blockDim.x) {
+            if (i < S * NP + P)
+                atomicAdd(&out[i], red[i]);
+            else if (red[i])
+                atomicOr(&out[i], red[i]);
+        }
+        return;
+    }
+    // ---- 4. one workgroup holds the whole configuration: counts and Eq. 2-3 here ----
+    int32_t *cnt = counts_out + kc * (int64_t)(S * M * M);
+    // epilogue scratch after the offset table: [S][M][M] counts, then [S][M][M] doubles
+    int32_t *lc = tab + 8 * bd.nh;
+    double *lsq = reinterpret_cast<double *>((reinterpret_cast<uintptr_t>(lc + S * M * M) + 7) & ~uintptr_t(7));
+    int64_t n[M];
+    {
+        int64_t rest = bd.N;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            n[i] = red[S * NP + i];
+            rest -= n[i];
+        }
+        n[M - 1] = rest;
+    }
+    const bool bad = red[S * NP + P] != 0;
+    if (threadIdx.x < S) {
+        const int k = threadIdx.x;
+        const int32_t *pa = red + k * NP;
+        int32_t *c = lc + k * M * M;
+        int q = 0;
+        for (int i = 0; i < P; ++i) {
+            c[i * M + i] = 2 * pa[q++];
+            for (int j = i + 1; j < P; ++j) {
+                c[i * M + j] = pa[q];
+                c[j * M + i] = pa[q];
+                ++q;
+            }
+        }
+        int64_t last = 0;
+        for (int i = 0; i < P; ++i) {
+            int64_t r = (int64_t)bd.zk[k] * n[i];
+            for (int j = 0; j < P; ++j) r -= c[i * M + j];
+            c[i * M + (M - 1)] = (int32_t)r;
+            c[(M - 1) * M + i] = (int32_t)r;
+            last += r;
+        }
+        c[(M - 1) * M + (M - 1)] = (int32_t)((int64_t)bd.zk[k] * n[M - 1] - last);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < S * M * M; e += blockDim.x) {
+        cnt[e] = lc[e];
+        if (S_F) {
+            const int k = e / (M * M), i = (e / M) % M, j = e % M;
+            const double R = (double)bd.N / (double)(n[i] * n[j] * (int64_t)bd.zk[k]);
+            const double a = 1.0 - (double)lc[e] * R;
+            const double dd = a - tw[e];
+            lsq[e] = dd * dd;
+        }
+    }
+    if (threadIdx.x == 0) bad_out[kc] = bad ? 1 : 0;
+    if (S_F) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            bool ok = !bad;
+#pragma unroll
+            for (int i = 0; i < M; ++i) ok = ok && n[i] > 0;
+            double sum = 0.0;
+            for (int k = 0; k < S; ++k) {
+                double Q = 0.0;
+                for (int i = 0; i < M; ++i) {
+                    double row = 0.0;
+                    for (int j = 0; j < M; ++j) row = row + lsq[(k * M + i) * M + j];
+                    Q = Q + row;
+                }
+                sum = sum + tw[S * M * M + k] * Q;
+            }
+            const double nan = __longlong_as_double(0x7ff8000000000000ll);
+            S_F[2 * kc] = ok ? sum : nan;
+            S_F[2 * kc + 1] = ok ? sqrt(sum) : nan;
+        }
     }
 }
 
@@ -325,10 +402,11 @@ __global__ void zero_kernel(int32_t *p, int64_t n) {
 }
 
 template <int M, int S>
-hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_t *partial,
-                     int32_t *counts, int32_t *bad, hipStream_t stream) {
+hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_t *partial, int32_t *counts,
+                     int32_t *bad, const double *tw, double *S_F, hipStream_t stream) {
     const int P = M - 1;
-    const size_t lds = ((size_t)(bd.ZC + 1) * 4 * P * bd.PW + bd.LW + S * Pairs<M>::NP + P + 1 + 8 * bd.nh) * 4;
+    const size_t lds = ((size_t)(bd.ZC + 1) * 4 * P * bd.PW + bd.LW + S * Pairs<M>::NP + P + 1 + 8 * bd.nh + 1 +
+                        3 * S * M * M + 2) * 4;
     const void *fn = (const void *)count_bits_kernel<M, S>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -340,15 +418,17 @@ hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_
     for (int64_t k0 = 0; k0 < K; k0 += 65535) {
         const int64_t kn = std::min<int64_t>(65535, K - k0);
         hipLaunchKernelGGL((count_bits_kernel<M, S>), dim3(bd.nchunks, (unsigned)kn), dim3(bd.threads), lds, stream,
-                           bd, kn, species + k0 * (int64_t)bd.N, partial + k0 * bd.partial_stride);
+                           bd, kn, species + k0 * (int64_t)bd.N, partial + k0 * bd.partial_stride,
+                           counts + k0 * (int64_t)(S * M * M), bad + k0, tw, S_F ? S_F + 2 * k0 : nullptr);
     }
-    hipLaunchKernelGGL((finalize_bits_kernel<M, S>), dim3((unsigned)((K + 127) / 128)), dim3(128), 0, stream, bd, K,
-                       partial, counts, bad);
+    if (bd.nchunks > 1)
+        hipLaunchKernelGGL((finalize_bits_kernel<M, S>), dim3((unsigned)((K + 127) / 128)), dim3(128), 0, stream, bd, K,
+                           partial, counts, bad);
     return hipGetLastError();
 }
 
 using LaunchFn = hipError_t (*)(const BitDesc &, int64_t, const int8_t *, int32_t *, int32_t *, int32_t *,
-                                hipStream_t);
+                                const double *, double *, hipStream_t);
 
 template <int M>
 LaunchFn pick_s(int S) {
@@ -396,7 +476,7 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, BitDesc *bd) {
     bd->partial_stride = ((g.S * np + P + 1) + 3) & ~3;
     for (int k = 0; k < kMaxShells; ++k) bd->zk[k] = k < g.S ? g.z[k] : 0;
     // largest z-chunk whose planes fit in LDS
-    const int fixed = (bd->LW + g.S * np + P + 1 + 8 * kMaxOffsets / 2) * 4;
+    const int fixed = (bd->LW + g.S * np + P + 1 + 8 * kMaxOffsets / 2 + 3 * g.S * g.M * g.M + 3) * 4;
     const int per_layer = 4 * P * bd->PW * 4;
     int zc = (lds_budget - fixed) / per_layer - 1;
     if (zc < 1) return false;
@@ -435,10 +515,11 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, BitDesc *bd) {
 }
 
 hipError_t launch_count_bits(const Geometry &g, const BitDesc &bd, int64_t K, const int8_t *species,
-                             int32_t *partial, int32_t *counts, int32_t *bad, hipStream_t stream) {
+                             int32_t *partial, int32_t *counts, int32_t *bad, const double *tw, double *S_F,
+                             hipStream_t stream) {
     LaunchFn f = pick(g.M, g.S);
     if (!f) return hipErrorInvalidValue;
-    return f(bd, K, species, partial, counts, bad, stream);
+    return f(bd, K, species, partial, counts, bad, tw, S_F, stream);
 }
 
 }  // namespace pyhea
