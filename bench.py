@@ -2,12 +2,19 @@
 
 Workload (one "step" = one pass over the whole hot path):
   * full SRO evaluation of a batch of K independent FCC 20x20x20 configurations
-    (32,000 sites, 5 species, shells 1-3) in one launch;
+    (32,000 sites, 5 species, shells 1-3) in one launch, of one such configuration
+    alone (latency), and of 4,096 FCC 40x40x40 configurations (256,000 sites,
+    4 species, shells 1-2);
   * the plain single chain of that shape: 5 equiatomic species, target alpha 0,
     unit weights, 10^6 Philox trial swaps, B = 64, disjoint commits;
   * the batched form: 512 chains of uneven FCC/BCC cells (250-16,000 sites,
     3-6 species, 10^5 trials each) in one persistent launch.
 Inputs are synthetic, seeded and resident in HBM before the timed region.
+
+After the timed steps the same 512 chains run once more one after another
+through the single-chain entry point ("plain"), and their final configurations
+must equal the batched ones; then 2,000 jobs are served with Poisson arrivals
+at 70 % of the measured batched capacity (p50/p99 of completion - arrival).
 
 Prints one JSON line: value = trial swaps/s of the single chain; the full
 evaluation's GB/s (with the HBM roofline of its kernel) and the batched
@@ -38,7 +45,11 @@ def parse():
     ap.add_argument("--eval-configs", type=int, default=32768)
     ap.add_argument("--chains", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="eval,chain,batch")
+    ap.add_argument("--legs", default="eval,eval3,lat,chain,batch")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain (one after another) chains")
+    ap.add_argument("--serve-jobs", type=int, default=2000, help="served jobs (0 = skip serving)")
+    ap.add_argument("--serve-budget-mb", type=int, default=64)
+    ap.add_argument("--serve-load", type=float, default=0.7, help="offered load / batched capacity")
     return ap.parse_args()
 
 
@@ -89,6 +100,43 @@ def recorded_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
+def serve(pb, wl, n_jobs, capacity_trials_per_s, load, budget_mb):
+    """Poisson arrivals of jobs (2,000-2,000,000 sites, 10^4-10^7 trials) at
+    `load` times the measured batched capacity; latency = completion - arrival."""
+    jobs = wl.config5_jobs(n_jobs=n_jobs)
+    T = np.array([j.n_trials for j in jobs], dtype=np.float64)
+    rate = load * capacity_trials_per_s / T.mean()
+    arrivals = wl.poisson_arrivals(len(jobs), rate)
+    res = {}
+    with pb.Server(hbm_budget_bytes=budget_mb << 20, max_slots=1024, steps_per_round=256) as srv:
+        t0 = time.perf_counter()
+        for i, j in enumerate(jobs):
+            while True:
+                wait = t0 + arrivals[i] - time.perf_counter()
+                if wait <= 0:
+                    break
+                time.sleep(min(wait, 1e-3))
+            srv.pyhea_serve_submit(i, j.lattice, j.L, j.M, j.S, j.target, j.weight, j.species,
+                                   pb.make_params(j.seed, i, j.n_trials, j.B))
+        for i, j in enumerate(jobs):
+            res[i] = srv.pyhea_serve_poll(i, j.N)
+        c = srv.pyhea_serve_counters()
+    bad = [i for i, r in res.items() if r[0] != pb.OK]
+    if bad:
+        print(f"served jobs failed: {bad[:10]}", file=sys.stderr)
+        sys.exit(1)
+    sub = np.array([r[3][0] for r in res.values()], dtype=np.float64)
+    fin = np.array([r[3][2] for r in res.values()], dtype=np.float64)
+    lat = (fin - sub) / 1e6
+    trials = sum(r[2]["trials"] for r in res.values())
+    span = (fin.max() - sub.min()) / 1e9
+    return {"jobs": len(jobs), "offered_jobs_per_s": rate, "offered_load": load,
+            "capacity_trials_per_s": capacity_trials_per_s, "hbm_budget_MB": budget_mb,
+            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+            "latency_ms_max": float(lat.max()), "trials": int(trials), "span_s": span,
+            "trials_per_s": trials / span, "rounds": c["rounds"], "sites_total": int(sum(j.N for j in jobs))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -134,6 +182,20 @@ def main():
     bpars = [pb.make_params(c.seed, c.chain_id, c.n_trials, c.B) for c in chains]
     b_trials = sum(c.n_trials for c in chains)
 
+    p3 = wl.config3()
+    K3 = 4096
+    eval3_in = None
+    if "eval3" in legs:
+        blk = torch.from_numpy(wl.iid_configs(p3.N, p3.M, 256, seed=4)).cuda()
+        g3 = torch.Generator(device="cuda").manual_seed(5)
+        eval3_in = torch.cat([blk] + [blk[:, torch.randperm(p3.N, device="cuda", generator=g3)]
+                                      for _ in range(K3 // 256 - 1)]).contiguous()
+        counts3 = torch.zeros((K3, p3.S, p3.M, p3.M), dtype=torch.int32, device="cuda")
+        S_F3 = torch.zeros((K3, 2), dtype=torch.float64, device="cuda")
+    lat_counts = torch.zeros((1, S, M, M), dtype=torch.int32, device="cuda")
+    lat_SF = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+    lat_reps = 20
+
     copy_dst = torch.empty_like(eval_in) if "copy" in legs else None
 
     def step(ev):
@@ -143,6 +205,16 @@ def main():
             ev["eval0"].record(stream)
             pb.pyhea_sro_eval_batch(p.lattice, p.L, M, S, eval_in, counts, p.target, p.weight, S_F)
             ev["eval1"].record(stream)
+        if "eval3" in legs:
+            ev["eval30"].record(stream)
+            pb.pyhea_sro_eval_batch(p3.lattice, p3.L, p3.M, p3.S, eval3_in, counts3, p3.target, p3.weight, S_F3)
+            ev["eval31"].record(stream)
+        if "lat" in legs:
+            ev["lat0"].record(stream)
+            for _ in range(lat_reps):
+                pb.pyhea_sro_eval_batch(p.lattice, p.L, M, S, chain0.view(1, -1), lat_counts, p.target,
+                                        p.weight, lat_SF)
+            ev["lat1"].record(stream)
         if "chain" in legs:
             chain.copy_(chain0)
             ev["chain0"].record(stream)
@@ -155,7 +227,7 @@ def main():
             ev["batch_stats"] = pb.pyhea_mc_batch(bprobs, bspecies, boff, bpars)
             ev["batch1"].record(stream)
 
-    names = ["eval0", "eval1", "chain0", "chain1", "batch0", "batch1"]
+    names = ["eval0", "eval1", "eval30", "eval31", "lat0", "lat1", "chain0", "chain1", "batch0", "batch1"]
     for _ in range(args.warmup):
         step({n: torch.cuda.Event(enable_timing=True) for n in names})
     torch.cuda.synchronize()
@@ -195,6 +267,15 @@ def main():
                            "frac": gbps / HBM_PEAK_GBPS,
                            "traffic": None if tb is None else tb / (ms.mean() / 1e3) / 1e9,
                            "kernel": "full SRO evaluation (pair counts + objective) of the batch"}
+    if "eval3" in legs:
+        ms = np.array(leg_ms("eval30", "eval31"))
+        gbps = K3 * (p3.N + p3.S * p3.M * p3.M * 4 + 16) / (ms.mean() / 1e3) / 1e9
+        out["sro_eval_fcc40"] = {"GBps": gbps, "configs_per_s": K3 / (ms.mean() / 1e3), "ms": float(ms.mean()),
+                                 "frac_hbm": gbps / HBM_PEAK_GBPS, "configs": K3,
+                                 "workload": "FCC 40x40x40 (256,000 sites), 4 species, shells 1-2"}
+    if "lat" in legs:
+        ms = np.array(leg_ms("lat0", "lat1"))
+        out["sro_eval_one_config_us"] = float(ms.mean() * 1e3 / lat_reps)
     if "batch" in legs:
         ms = np.array(leg_ms("batch0", "batch1"))
         bst = evs[-1]["batch_stats"]
@@ -203,7 +284,30 @@ def main():
                           "chains": len(chains), "trials": b_trials,
                           "mean_final_F": float(fs.mean())}
         if "chain" in legs:
-            out["batched"]["vs_plain_chain"] = out["batched"]["trials_per_s"] / out["value"]
+            out["batched"]["vs_fcc20_chain"] = out["batched"]["trials_per_s"] / out["value"]
+        if not args.no_plain:
+            # the same chains one after another through the single-chain entry point
+            batched_final = bspecies.clone()
+            bspecies.copy_(bspecies0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for i, c in enumerate(chains):
+                view = bspecies[boff[i]:boff[i + 1]]
+                pb.pyhea_mc_run(c.lattice, c.L, c.M, c.S, c.target, c.weight, view, bpars[i], None)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            pms = e0.elapsed_time(e1)
+            same = bool(torch.equal(bspecies, batched_final))
+            out["batched"]["plain_ms"] = pms
+            out["batched"]["plain_trials_per_s"] = b_trials / (pms / 1e3)
+            out["batched"]["vs_plain"] = pms / float(ms.mean())
+            out["batched"]["plain_final_equal"] = same
+            if not same:
+                print("batched and plain chains ended in different configurations", file=sys.stderr)
+                sys.exit(1)
+    if args.serve_jobs > 0:
+        cap = out.get("batched", {}).get("trials_per_s", 1.0e9)
+        out["serving"] = serve(pb, wl, args.serve_jobs, cap, args.serve_load, args.serve_budget_mb)
     if "value" not in out:
         out["value"] = None
     if not args.no_cpu_baseline:

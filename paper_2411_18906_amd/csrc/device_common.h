@@ -74,6 +74,15 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
     return __longlong_as_double(((uint64_t)hi << 32) | lo);
 }
 
+// value of v in lane src (any lane index per lane; one LDS permute per half)
+__device__ __forceinline__ double shfl_f64(double v, int src) {
+    const uint64_t u = __double_as_longlong(v);
+    const int addr = (src & 63) << 2;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(u >> 32));
+    return __longlong_as_double(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ uint64_t ballot64(bool pred) { return __ballot(pred); }
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }

@@ -16,8 +16,8 @@ __host__ __device__ inline int mc_lds_bytes(int S, int M, int B, int H = 1) {
     n += r(kMaxOffsets * 16) + r(kMaxOffsets * 4);     // dlin4, offmod
     n += r(B * 8) + 5 * r(B * 4);                 // rec_dS, p, q, pp, pq, ab
     n += 3 * r(S * B * 8);                        // rec_cp, rec_cq, rec_dQ
-    n += 2 * r(B * 4) + r(2 * B * 4);             // order, list, cpos
-    n += r(kMaxShells * 8) + r(16 * 4);           // sh_dQ, sh_int
+    n += 2 * r(B * 4);                            // order, list
+    n += r(2 * kMaxShells * 8) + r(16 * 4);       // sh_dQ (two buffers), sh_int
     if (H == 2) n += r(2 * 2 * S * B * 8) + r(S * B * 4 * 8);  // partial histograms, row sums
     return n;
 }
@@ -37,6 +37,8 @@ hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M,
                      int lds_bytes, int max_steps, hipStream_t stream);
 hipError_t launch_pad_fill(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);
 hipError_t launch_pad_drain(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);
+// out[i] = *descs_dev[i].state (device array of n_chains states).
+hipError_t launch_gather_states(const ChainDesc *descs_dev, int n_chains, ChainState *out, hipStream_t stream);
 
 // Full evaluation: pair counts of K configurations of one geometry.
 struct EvalDesc {
@@ -53,6 +55,21 @@ struct EvalDesc {
 };
 
 void fill_eval_desc(const Geometry &g, EvalDesc *d);
+
+// One configuration of a many-chain count launch (each its own geometry).
+struct CountTask {
+    EvalDesc ed;
+    const int8_t *species;  // N sites, unpadded
+    int32_t *counts;        // [S][M][M], zero before the launch
+    int32_t *bad;           // set to 1 if a species id lies outside [0, M); zero before the launch
+};
+constexpr int kCountTile = 2048;  // sites per workgroup of the many-chain count
+inline uint32_t count_tiles(uint32_t N) { return (N + kCountTile - 1) / kCountTile; }
+
+// Pair counts of n configurations with different geometries in one launch.
+// tile0[c] = first tile of task c (prefix sums of count_tiles), n_tiles = total.
+hipError_t launch_count_tasks(const CountTask *tasks, const uint32_t *tile0, int n, uint32_t n_tiles,
+                              hipStream_t stream);
 
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t stream);
 

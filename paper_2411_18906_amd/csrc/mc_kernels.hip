@@ -78,8 +78,7 @@ struct Lds {
     double *rec_dQ;     // [S][B]
     int32_t *order;     // [B]
     int32_t *list;      // [B]
-    uint32_t *cpos;     // [2B] committed site positions
-    double *sh_dQ;      // [kMaxShells]
+    double *sh_dQ;      // [2][kMaxShells]
     int32_t *sh_int;    // scalars
     uint64_t *part;     // [S][2 halves][2 (cp, cq)][B] partial histograms (H == 2)
     double *rowbuf;     // [S][B][4] row sums of the second half (H == 2)
@@ -170,17 +169,15 @@ __device__ __forceinline__ bool near_or_equal(const ChainDesc &d, uint32_t u, ui
     return hit;
 }
 
-// write species v at site (cx, cy, cz, b) and at every halo copy of it: padded
-// coordinates x0 + i*Lx < PX per axis (at most 5 per axis), one lane per copy
+// species v at site (cx, cy, cz, b) and at every halo copy of it: padded
+// coordinates x0 + i*L < P per axis
 template <int kStore>
-__device__ void write_site(const Lds &L, const ChainDesc &d, int cx, int cy, int cz, int b, int v,
-                           int lane) {
+__device__ void write_site(const Lds &L, const ChainDesc &d, int cx, int cy, int cz, int b, int v) {
     const int h = d.halo;
     const int x0 = wrap_axis(cx + h, d.Lx), y0 = wrap_axis(cy + h, d.Ly), z0 = wrap_axis(cz + h, d.Lz);
-    for (int t = lane; t < 512; t += kWave) {
-        const int px = x0 + (t & 7) * d.Lx, py = y0 + ((t >> 3) & 7) * d.Ly, pz = z0 + (t >> 6) * d.Lz;
-        if (px < d.PX && py < d.PY && pz < d.PZ) store_species<kStore>(L, d, padded_id(d, px, py, pz, b), v);
-    }
+    for (int pz = z0; pz < d.PZ; pz += d.Lz)
+        for (int py = y0; py < d.PY; py += d.Ly)
+            for (int px = x0; px < d.PX; px += d.Lx) store_species<kStore>(L, d, padded_id(d, px, py, pz, b), v);
 }
 
 __device__ __forceinline__ int sel4(int4 v, int b) {
@@ -224,8 +221,7 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
         L.rec_dQ = (double *)carve(p, S * B * 8);
         L.order = (int32_t *)carve(p, B * 4);
         L.list = (int32_t *)carve(p, B * 4);
-        L.cpos = (uint32_t *)carve(p, 2 * B * 4);
-        L.sh_dQ = (double *)carve(p, kMaxShells * 8);
+        L.sh_dQ = (double *)carve(p, 2 * kMaxShells * 8);
         L.sh_int = (int32_t *)carve(p, 16 * 4);
         if (H == 2) {
             L.part = (uint64_t *)carve(p, 2 * 2 * S * B * 8);
@@ -295,6 +291,10 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
     const int r1 = H == 2 ? (lead ? RH : M) : M;
     const int G = (B + kWave - 1) / kWave;
     if (trials >= d.n_trials) done = true;
+    double wk[kMaxShells];
+#pragma unroll
+    for (int kk = 0; kk < kMaxShells; ++kk) wk[kk] = d.w[kk];
+    const double tau = d.tau;
 
     for (int it = 0; it < max_steps && !done; ++it) {
         const int64_t left = d.n_trials - trials;
@@ -440,6 +440,8 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
         if (wave == 0) {
             int n_impr = 0;
             int step_nulls = 0;
+            double my_dS = 0.0;
+            uint64_t imp_mask = 0;
             for (int g = 0; g < G; ++g) {
                 const int s = g * kWave + lane;
                 bool imp = false;
@@ -447,9 +449,12 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                     const uint32_t ab = L.rec_ab[s];
                     const bool act = (ab >> 17) & 1u, nul = (ab >> 16) & 1u;
                     double dS = 0.0;
-                    for (int kk = 0; kk < S; ++kk) dS = dS + d.w[kk] * L.rec_dQ[kk * B + s];
+#pragma unroll
+                    for (int kk = 0; kk < kMaxShells; ++kk)
+                        if (kk < S) dS = dS + wk[kk] * L.rec_dQ[kk * B + s];
                     L.rec_dS[s] = dS;
-                    imp = act && !nul && (dS < -d.tau);
+                    if (G == 1) my_dS = dS;
+                    imp = act && !nul && (dS < -tau);
                     step_nulls += (int)__popcll(ballot64(act && nul));
                 } else {
                     step_nulls += (int)__popcll(ballot64(false));
@@ -458,49 +463,70 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                 const int before = (int)__popcll(mask & ((1ull << lane) - 1ull));
                 if (imp) L.list[n_impr + before] = s;
                 n_impr += (int)__popcll(mask);
+                imp_mask = mask;
             }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_s_waitcnt(0);
-            for (int idx = lane; idx < n_impr; idx += kWave) {
-                const int s = L.list[idx];
-                const double ds = L.rec_dS[s];
+            if (G == 1) {
+                // rank by (dS, slot) with the improving slots' dS read across lanes
                 int rank = 0;
-                for (int j = 0; j < n_impr; ++j) {
-                    const int s2 = L.list[j];
-                    const double d2 = L.rec_dS[s2];
-                    rank += (d2 < ds || (d2 == ds && s2 < s)) ? 1 : 0;
+                for (uint64_t m = imp_mask; m; m &= m - 1) {
+                    const int l = __ffsll((long long)m) - 1;
+                    const double d2 = readlane_f64(my_dS, l);
+                    rank += (d2 < my_dS || (d2 == my_dS && l < lane)) ? 1 : 0;
                 }
-                L.order[rank] = s;
+                if ((imp_mask >> lane) & 1ull) L.order[rank] = lane;
+            } else {
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_s_waitcnt(0);
+                for (int idx = lane; idx < n_impr; idx += kWave) {
+                    const int s = L.list[idx];
+                    const double ds = L.rec_dS[s];
+                    int rank = 0;
+                    for (int j = 0; j < n_impr; ++j) {
+                        const int s2 = L.list[j];
+                        const double d2 = L.rec_dS[s2];
+                        rank += (d2 < ds || (d2 == ds && s2 < s)) ? 1 : 0;
+                    }
+                    L.order[rank] = s;
+                }
             }
             if (lane == 0) L.sh_int[0] = n_impr;
             nulls += step_nulls;  // only thread 0's copy is stored
         }
         __syncthreads();
 
-        // ---- phase 3: commits (all waves in lock step) -------------------------------
+        // ---- phase 3: commits ---------------------------------------------------------
+        // Candidates in rank order.  A candidate within shells 1..S of an earlier
+        // commit of this step is skipped; the others keep their neighbour
+        // histograms, so re-validation needs only the running counts.  Every wave
+        // keeps the committed positions in registers (position 2c + {0,1} of
+        // commit c in lane (2c) % 64 of register (2c) / 64) and reaches the same
+        // decisions; shell k's entries belong to one wave, and the waves meet once
+        // per re-validated candidate to add the shells' dQ.  Site writes wait
+        // until the end of the phase: later candidates never read committed sites.
         const int n_impr = L.sh_int[0];
         int n_commit = 0;
+        int n_meet = 0;
+        uint32_t cpr[kMaxB / 32];
+#pragma unroll
+        for (int r = 0; r < kMaxB / 32; ++r) cpr[r] = 0;
+        const bool ewave = grp == 0 && lead;   // one wave per shell handles its entries
         for (int u = 0; u < n_impr; ++u) {
             if (d.mode == PYHEA_MODE_BEST && n_commit > 0) break;
             const int s = L.order[u];
             const uint32_t upp = L.rec_pp[s], upq = L.rec_pq[s];
-            bool conflict = false;
-            for (int c0 = 0; c0 < 2 * n_commit; c0 += kWave) {
-                const int c = c0 + lane;
-                bool hit = false;
-                if (c < 2 * n_commit) {
-                    const uint32_t v = L.cpos[c];
-                    hit = near_or_equal(d, upp, v) || near_or_equal(d, upq, v);
-                }
-                conflict |= ballot64(hit) != 0;
+            bool hit = false;
+#pragma unroll
+            for (int r = 0; r < kMaxB / 32; ++r) {
+                if (r * kWave >= 2 * n_commit) break;
+                if (r * kWave + lane < 2 * n_commit)
+                    hit |= near_or_equal(d, upp, cpr[r]) || near_or_equal(d, upq, cpr[r]);
             }
-            if (conflict) continue;
+            if (ballot64(hit) != 0) continue;
             const uint32_t ab = L.rec_ab[s];
             const int a = (int)(ab & 0xFFu), b = (int)((ab >> 8) & 0xFFu);
-            // this wave's shell-k change of entry e = lane (waves 0..S-1 only)
+            // this wave's shell-k change of entry e = lane (the S entry waves only)
             int dn = 0;
             int e = 0;
-            const bool ewave = grp == 0 && lead;   // one wave per shell handles its entries
             if (ewave && lane < M * M) {
                 const Hist cp = (Hist)L.rec_cp[k * B + s], cq = (Hist)L.rec_cq[k * B + s];
                 const int i = lane / M, j = lane - (lane / M) * M;
@@ -510,66 +536,80 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
             }
             bool ok = true;
             if (n_commit > 0) {
+                double *dq = L.sh_dQ + (n_meet & 1) * kMaxShells;   // alternating buffers
                 if (ewave) {
                     double delta = 0.0;
                     if (dn != 0) {
                         const Ent en = L.ent[e];
                         delta = sq_dev(en.cnt + dn, en.R, en.t) - en.sq;
                     }
-                    // row sums, then their sum (entries with dN = 0 add exactly +0.0)
-                    uint64_t mask = ballot64(dn != 0);
-                    double acc = 0.0, rs = 0.0;
-                    int cur = -1;
-                    while (mask) {
-                        const int l = __ffsll((long long)mask) - 1;
-                        const int r = l / M;
-                        if (r != cur) {
-                            acc = acc + rs;
-                            rs = 0.0;
-                            cur = r;
-                        }
-                        rs = rs + readlane_f64(delta, l);
-                        mask &= mask - 1;
-                    }
-                    acc = acc + rs;
-                    if (lane == 0) L.sh_dQ[k] = acc;
+                    // row i summed in lane i over j in order, then the rows in order.
+                    // Entries with dN = 0 hold +0.0; a sum that starts at +0.0 never
+                    // becomes -0.0 (deltas are never -0.0), so adding them is exact.
+                    double rs = 0.0;
+#pragma unroll
+                    for (int j = 0; j < M; ++j) rs = rs + shfl_f64(delta, lane * M + j);
+                    double acc = 0.0;
+#pragma unroll
+                    for (int i = 0; i < M; ++i) acc = acc + readlane_f64(rs, i);
+                    if (lane == 0) dq[k] = acc;
                 }
                 __syncthreads();
+                double q[kMaxShells];
+#pragma unroll
+                for (int kk = 0; kk < kMaxShells; ++kk) q[kk] = kk < S ? dq[kk] : 0.0;
                 double dS = 0.0;
-                for (int kk = 0; kk < S; ++kk) dS = dS + d.w[kk] * L.sh_dQ[kk];
-                ok = dS < -d.tau;
-                __syncthreads();
+#pragma unroll
+                for (int kk = 0; kk < kMaxShells; ++kk)
+                    if (kk < S) dS = dS + wk[kk] * q[kk];
+                ok = dS < -tau;
+                ++n_meet;
             }
             if (!ok) continue;
-            // apply: counts and squared deviations of shell k, species, log
+            // apply: counts and squared deviations of shell k (wave-private entries)
             if (ewave && dn != 0) {
                 Ent en = L.ent[e];
                 en.cnt += dn;
                 en.sq = sq_dev(en.cnt, en.R, en.t);
                 L.ent[e] = en;
             }
-            if (wave == 0) {
-                const uint32_t p = L.rec_p[s], q = L.rec_q[s];
-                const SiteCoord sp = site_coord(p, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
-                const SiteCoord sq = site_coord(q, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
-                write_site<kStore>(L, d, sp.cx, sp.cy, sp.cz, sp.b, b, lane);
-                write_site<kStore>(L, d, sq.cx, sq.cy, sq.cz, sq.b, a, lane);
-                if (lane == 0) {
-                    if (d.log && commits < d.log_cap) {
-                        uint32_t *rec = d.log + 4 * commits;
-                        rec[0] = (uint32_t)step;
-                        rec[1] = (uint32_t)s;
-                        rec[2] = p;
-                        rec[3] = q;
+            {
+                const int c0 = 2 * n_commit, r0 = c0 / kWave;
+#pragma unroll
+                for (int r = 0; r < kMaxB / 32; ++r)
+                    if (r == r0) {
+                        cpr[r] = lane == (c0 & (kWave - 1)) ? upp : cpr[r];
+                        cpr[r] = lane == ((c0 + 1) & (kWave - 1)) ? upq : cpr[r];
                     }
-                    L.cpos[2 * n_commit] = upp;
-                    L.cpos[2 * n_commit + 1] = upq;
+            }
+            if (threadIdx.x == 0) L.list[n_commit] = s;
+            ++n_commit;
+        }
+        __syncthreads();
+        // the committed swaps: every copy of both sites, and the log
+        for (int t = threadIdx.x; t < n_commit * 2; t += nthreads) {
+            const int s = L.list[t >> 1];
+            const int side = t & 1;
+            const uint32_t ab = L.rec_ab[s];
+            const uint32_t site = side ? L.rec_q[s] : L.rec_p[s];
+            const int v = side ? (int)(ab & 0xFFu) : (int)((ab >> 8) & 0xFFu);
+            const SiteCoord sc = site_coord(site, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
+            write_site<kStore>(L, d, sc.cx, sc.cy, sc.cz, sc.b, v);
+        }
+        if (d.log) {
+            for (int c = threadIdx.x; c < n_commit; c += nthreads) {
+                const int64_t at = commits + c;
+                if (at < d.log_cap) {
+                    const int s = L.list[c];
+                    uint32_t *rec = d.log + 4 * at;
+                    rec[0] = (uint32_t)step;
+                    rec[1] = (uint32_t)s;
+                    rec[2] = L.rec_p[s];
+                    rec[3] = L.rec_q[s];
                 }
             }
-            ++n_commit;
-            ++commits;
-            __syncthreads();
         }
+        commits += n_commit;
 
         // ---- phase 4: bookkeeping --------------------------------------------------
         trials += tasks;
@@ -607,6 +647,12 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
 }
 
 // padded HBM copy <-> unpadded configuration (HBM-resident chains)
+// Chain states of many chains into one contiguous array (one read-back).
+__global__ void gather_states_kernel(const ChainDesc *__restrict__ descs, int n, ChainState *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = *descs[i].state;
+}
+
 __global__ void pad_fill_kernel(const ChainDesc *__restrict__ descs) {
     const ChainDesc &d = descs[blockIdx.y];
     if (d.store != kStoreGlobal) return;
@@ -656,6 +702,13 @@ hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M,
     if (e != hipSuccess) return e;
     void *args[] = {(void *)&descs_dev, (void *)&max_steps, (void *)&H};
     return hipLaunchKernel(fn, grid, block, args, (size_t)lds_bytes, stream);
+}
+
+hipError_t launch_gather_states(const ChainDesc *descs_dev, int n_chains, ChainState *out, hipStream_t stream) {
+    if (n_chains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_states_kernel, dim3((n_chains + 255) / 256), dim3(256), 0, stream, descs_dev, n_chains,
+                       out);
+    return hipGetLastError();
 }
 
 hipError_t launch_pad_fill(const ChainDesc *descs_dev, int n_chains, hipStream_t stream) {

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 
 #include "autotune.h"
@@ -165,6 +166,66 @@ struct DeviceBuffer {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Auxiliary streams (default priority, non-blocking) on which launches of
+// different shapes run side by side; created once per device, kept until exit.
+constexpr int kAuxStreams = 4;
+
+bool aux_streams(hipStream_t *out) {
+    static std::mutex mu;
+    static hipStream_t pool[64][kAuxStreams];
+    static bool made[64] = {false};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!made[dev]) {
+        for (int i = 0; i < kAuxStreams; ++i)
+            if (hipStreamCreateWithFlags(&pool[dev][i], hipStreamNonBlocking) != hipSuccess) return false;
+        made[dev] = true;
+    }
+    for (int i = 0; i < kAuxStreams; ++i) out[i] = pool[dev][i];
+    return true;
+}
+
+// Events that fork work from `main` onto aux streams and join it back.
+struct Fork {
+    hipStream_t main = nullptr;
+    hipStream_t aux[kAuxStreams] = {};
+    int used = 0;
+    std::vector<hipEvent_t> events;
+    ~Fork() {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    }
+    hipError_t begin(hipStream_t m, int n_streams) {
+        main = m;
+        used = std::min(n_streams, kAuxStreams);
+        if (used <= 1 || !aux_streams(aux)) {
+            used = 0;  // everything stays on the caller's stream
+            return hipSuccess;
+        }
+        hipEvent_t e;
+        hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (r != hipSuccess) return r;
+        events.push_back(e);
+        if ((r = hipEventRecord(e, main)) != hipSuccess) return r;
+        for (int i = 0; i < used; ++i)
+            if ((r = hipStreamWaitEvent(aux[i], e, 0)) != hipSuccess) return r;
+        return hipSuccess;
+    }
+    hipStream_t stream(int i) const { return used ? aux[i % used] : main; }
+    hipError_t end() {
+        for (int i = 0; i < used; ++i) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+            if (r != hipSuccess) return r;
+            events.push_back(e);
+            if ((r = hipEventRecord(e, aux[i])) != hipSuccess) return r;
+            if ((r = hipStreamWaitEvent(main, e, 0)) != hipSuccess) return r;
+        }
+        used = 0;
+        return hipSuccess;
+    }
+};
+
 }  // namespace
 
 pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
@@ -174,83 +235,64 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
     if (n == 0) return PYHEA_OK;
     const int lds_budget = max_lds_per_block();
 
-    // device arena: per chain counts, recount, bad flag, R, target, state, padded copy
-    struct Slot {
-        size_t counts, recount, bad, R, target, state, pad;
-        int store, lds, H;
-    };
-    std::vector<Slot> slot(n);
-    size_t total = 0;
+    // Device arena, in three blocks so that each crosses the bus in one copy:
+    //   X (read back): counts | recount | bad | bad2 | state     (zeroed on the device)
+    //   Y (uploaded before counting): target | descs | count tasks (initial, final) | tile0
+    //   Z (uploaded after counting): R
+    // followed by the padded HBM copies of chains that keep their configuration in HBM.
+    std::vector<size_t> eoff(n + 1, 0);
+    for (int c = 0; c < n; ++c) eoff[c + 1] = eoff[c] + (size_t)jobs[c].g.S * jobs[c].g.M * jobs[c].g.M;
+    const size_t Etot = eoff[n];
+    size_t off = 0;
+    const size_t o_counts = off;
+    off += Etot * 4;
+    const size_t o_recount = off;
+    off += Etot * 4;
+    const size_t o_bad = off;
+    off += (size_t)n * 4;
+    const size_t o_bad2 = off;
+    off += (size_t)n * 4;
+    off = (off + 7) & ~size_t(7);
+    const size_t o_state = off;
+    off += (size_t)n * sizeof(ChainState);
+    const size_t x_end = off;
+    off = align256(off);
+    const size_t y_begin = off;
+    const size_t o_target = off;
+    off += Etot * 8;
+    off = align256(off);
+    const size_t o_descs = off;
+    off += (size_t)n * sizeof(ChainDesc);
+    off = align256(off);
+    const size_t o_tasks = off;
+    off += (size_t)2 * n * sizeof(CountTask);
+    const size_t o_tile0 = off;
+    off += (size_t)n * 4;
+    const size_t y_end = off;
+    off = align256(off);
+    const size_t o_R = off;
+    off += Etot * 8;
+    std::vector<LaunchShape> shape(n);
+    std::vector<size_t> o_pad(n, 0);
     for (int c = 0; c < n; ++c) {
-        const Geometry &g = jobs[c].g;
-        const size_t E = (size_t)g.S * g.M * g.M;
-        Slot &s = slot[c];
-        s.counts = total;
-        total = align256(total + E * 4);
-        s.recount = total;
-        total = align256(total + E * 4);
-        s.bad = total;
-        total = align256(total + 4);
-        s.R = total;
-        total = align256(total + E * 8);
-        s.target = total;
-        total = align256(total + E * 8);
-        s.state = total;
-        total = align256(total + sizeof(ChainState));
-        const LaunchShape ls = choose_launch(g, jobs[c].params.cand_per_step, lds_budget, variant < 0 ? 0 : variant);
-        s.store = ls.store;
-        s.lds = ls.lds;
-        s.H = ls.H;
-        s.pad = total;
-        if (s.store == kStoreGlobal) total = align256(total + (size_t)g.Npad);
+        shape[c] = choose_launch(jobs[c].g, jobs[c].params.cand_per_step, lds_budget, variant < 0 ? 0 : variant);
+        if (shape[c].store == kStoreGlobal) {
+            off = align256(off);
+            o_pad[c] = off;
+            off += (size_t)jobs[c].g.Npad;
+        }
     }
     DeviceBuffer arena;
-    PYHEA_HIP(hipMalloc(&arena.ptr, total));
+    PYHEA_HIP(hipMalloc(&arena.ptr, off));
     char *base = (char *)arena.ptr;
 
-    // initial pair counts (full evaluation of each chain's configuration)
-    std::vector<EvalDesc> eds(n);
-    for (int c = 0; c < n; ++c) {
-        fill_eval_desc(jobs[c].g, &eds[c]);
-        const pyhea_status s = count_configs(jobs[c].g, 1, jobs[c].species_dev, (int32_t *)(base + slot[c].counts),
-                                             (int32_t *)(base + slot[c].bad), stream);
-        if (s != PYHEA_OK) return s;
-    }
-    std::vector<std::vector<int32_t>> cnt32(n);
-    std::vector<int32_t> bad(n);
-    for (int c = 0; c < n; ++c) {
-        const Geometry &g = jobs[c].g;
-        cnt32[c].resize((size_t)g.S * g.M * g.M);
-        PYHEA_HIP(hipMemcpyAsync(cnt32[c].data(), base + slot[c].counts, cnt32[c].size() * 4,
-                                 hipMemcpyDeviceToHost, stream));
-        PYHEA_HIP(hipMemcpyAsync(&bad[c], base + slot[c].bad, 4, hipMemcpyDeviceToHost, stream));
-    }
-    PYHEA_HIP(hipStreamSynchronize(stream));
-
-    std::vector<std::vector<double>> Rtab(n);
-    for (int c = 0; c < n; ++c) {
-        const Geometry &g = jobs[c].g;
-        std::vector<int64_t> c64(cnt32[c].begin(), cnt32[c].end());
-        int64_t nsp[kMaxSpecies];
-        if (bad[c] || !species_totals(g, c64.data(), nsp)) {
-            set_error("chain " + std::to_string(c) +
-                      ": species ids must lie in [0, n_species) and every species must occur");
-            return PYHEA_EINVAL;
-        }
-        Rtab[c].resize(c64.size());
-        ratio_table(g, nsp, Rtab[c].data());
-        ChainState st0;
-        std::memset(&st0, 0, sizeof(st0));
-        PYHEA_HIP(hipMemcpyAsync(base + slot[c].R, Rtab[c].data(), Rtab[c].size() * 8,
-                                 hipMemcpyHostToDevice, stream));
-        PYHEA_HIP(hipMemcpyAsync(base + slot[c].target, jobs[c].target.data(), jobs[c].target.size() * 8,
-                                 hipMemcpyHostToDevice, stream));
-        PYHEA_HIP(hipMemcpyAsync(base + slot[c].state, &st0, sizeof(st0), hipMemcpyHostToDevice, stream));
-    }
-
-    // descriptors, grouped by launch shape (store, M, S, B, H)
-    std::map<std::tuple<int, int, int, int, int>, std::vector<int>> groups;
+    // block Y on the host: targets, chain descriptors (ordered by launch group), count tasks
+    std::vector<char> hy(y_end - y_begin, 0);
+    auto hy_at = [&](size_t o) { return hy.data() + (o - y_begin); };
+    for (int c = 0; c < n; ++c)
+        std::memcpy(hy_at(o_target) + eoff[c] * 8, jobs[c].target.data(), jobs[c].target.size() * 8);
     std::vector<ChainDesc> descs(n);
+    std::map<std::tuple<int, int, int, int, int>, std::vector<int>> groups;
     for (int c = 0; c < n; ++c) {
         const ChainJob &j = jobs[c];
         ChainDesc &d = descs[c];
@@ -265,70 +307,116 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         d.tau = j.params.accept_tol;
         for (int k = 0; k < kMaxShells; ++k) d.w[k] = k < j.g.S ? j.weight[k] : 0.0;
         d.species = j.species_dev;
-        d.pad_global = slot[c].store == kStoreGlobal ? (int8_t *)(base + slot[c].pad) : nullptr;
-        d.R = (const double *)(base + slot[c].R);
-        d.target = (const double *)(base + slot[c].target);
-        d.counts = (int32_t *)(base + slot[c].counts);
+        d.pad_global = shape[c].store == kStoreGlobal ? (int8_t *)(base + o_pad[c]) : nullptr;
+        d.R = (const double *)(base + o_R) + eoff[c];
+        d.target = (const double *)(base + o_target) + eoff[c];
+        d.counts = (int32_t *)(base + o_counts) + eoff[c];
         d.log = j.log_dev;
         d.log_cap = j.log_dev ? j.log_cap : 0;
-        d.state = (ChainState *)(base + slot[c].state);
-        d.store = slot[c].store;
-        d.lds_bytes = slot[c].lds;
-        groups[{slot[c].store, j.g.M, j.g.S, d.B, slot[c].H}].push_back(c);
+        d.state = (ChainState *)(base + o_state) + c;
+        d.store = shape[c].store;
+        d.lds_bytes = shape[c].lds;
+        groups[{shape[c].store, j.g.M, j.g.S, d.B, shape[c].H}].push_back(c);
     }
-    DeviceBuffer dbuf;
-    PYHEA_HIP(hipMalloc(&dbuf.ptr, sizeof(ChainDesc) * n));
-    std::vector<ChainDesc> ordered;
-    ordered.reserve(n);
-    std::vector<std::pair<size_t, std::vector<int>>> launches;
-    for (auto &kv : groups) {
-        launches.push_back({ordered.size(), kv.second});
-        // longest chains first so the tail of the launch is short
-        std::vector<int> idx = kv.second;
-        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-            return jobs[a].params.n_trials > jobs[b].params.n_trials;
+    struct Launch {
+        int first, count, store, M, S, B, H, lds;
+    };
+    std::vector<Launch> launches;
+    {
+        ChainDesc *hd = (ChainDesc *)hy_at(o_descs);
+        int at = 0;
+        for (auto &kv : groups) {
+            // longest chains first so the tail of the launch is short
+            std::vector<int> idx = kv.second;
+            std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+                return jobs[a].params.n_trials > jobs[b].params.n_trials;
+            });
+            Launch L{at, (int)idx.size(), std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                     std::get<3>(kv.first), std::get<4>(kv.first), 0};
+            for (int c : idx) {
+                L.lds = std::max(L.lds, descs[c].lds_bytes);
+                hd[at++] = descs[c];
+            }
+            launches.push_back(L);
+        }
+        // the launch with the most work first, so it starts first
+        std::stable_sort(launches.begin(), launches.end(), [&](const Launch &a, const Launch &b) {
+            return a.count > b.count;
         });
-        launches.back().second = idx;
-        for (int c : idx) ordered.push_back(descs[c]);
     }
-    PYHEA_HIP(hipMemcpyAsync(dbuf.ptr, ordered.data(), sizeof(ChainDesc) * n, hipMemcpyHostToDevice, stream));
-    const ChainDesc *ddev = (const ChainDesc *)dbuf.ptr;
-    for (auto &L : launches) {
-        const int first = (int)L.first, count = (int)L.second.size();
-        const ChainDesc &d0 = descs[L.second[0]];
-        int lds = 0;
-        for (int c : L.second) lds = std::max(lds, descs[c].lds_bytes);
-        if (d0.store == kStoreGlobal) PYHEA_HIP(launch_pad_fill(ddev + first, count, stream));
-        PYHEA_HIP(launch_mc(ddev + first, count, d0.store, d0.M, d0.S, d0.B, slot[L.second[0]].H, lds, INT_MAX,
-                            stream));
-        if (d0.store == kStoreGlobal) PYHEA_HIP(launch_pad_drain(ddev + first, count, stream));
+    uint32_t n_tiles = 0;
+    {
+        CountTask *ht = (CountTask *)hy_at(o_tasks);
+        uint32_t *t0 = (uint32_t *)hy_at(o_tile0);
+        for (int c = 0; c < n; ++c) {
+            CountTask &a = ht[c], &b = ht[n + c];
+            fill_eval_desc(jobs[c].g, &a.ed);
+            a.species = jobs[c].species_dev;
+            a.counts = (int32_t *)(base + o_counts) + eoff[c];
+            a.bad = (int32_t *)(base + o_bad) + c;
+            b = a;
+            b.counts = (int32_t *)(base + o_recount) + eoff[c];
+            b.bad = (int32_t *)(base + o_bad2) + c;
+            t0[c] = n_tiles;
+            n_tiles += count_tiles((uint32_t)jobs[c].g.N);
+        }
+    }
+    PYHEA_HIP(launch_zero_i32((int32_t *)base, (int64_t)(x_end / 4), stream));
+    PYHEA_HIP(hipMemcpyAsync(base + y_begin, hy.data(), hy.size(), hipMemcpyHostToDevice, stream));
+    const CountTask *tasks = (const CountTask *)(base + o_tasks);
+    const uint32_t *tile0 = (const uint32_t *)(base + o_tile0);
+
+    // initial pair counts of every chain's configuration, in one launch
+    PYHEA_HIP(launch_count_tasks(tasks, tile0, n, n_tiles, stream));
+    std::vector<char> hx(x_end);
+    PYHEA_HIP(hipMemcpyAsync(hx.data(), base, o_bad2, hipMemcpyDeviceToHost, stream));
+    PYHEA_HIP(hipStreamSynchronize(stream));
+    const int32_t *cnt0 = (const int32_t *)(hx.data() + o_counts);
+    const int32_t *bad0 = (const int32_t *)(hx.data() + o_bad);
+    std::vector<double> Rtab(Etot);
+    for (int c = 0; c < n; ++c) {
+        const Geometry &g = jobs[c].g;
+        std::vector<int64_t> c64(cnt0 + eoff[c], cnt0 + eoff[c + 1]);
+        int64_t nsp[kMaxSpecies];
+        if (bad0[c] || !species_totals(g, c64.data(), nsp)) {
+            set_error("chain " + std::to_string(c) +
+                      ": species ids must lie in [0, n_species) and every species must occur");
+            return PYHEA_EINVAL;
+        }
+        ratio_table(g, nsp, Rtab.data() + eoff[c]);
+    }
+    PYHEA_HIP(hipMemcpyAsync(base + o_R, Rtab.data(), Etot * 8, hipMemcpyHostToDevice, stream));
+
+    // the chains: one launch per group, groups side by side on auxiliary streams
+    const ChainDesc *ddev = (const ChainDesc *)(base + o_descs);
+    {
+        Fork fork;
+        PYHEA_HIP(fork.begin(stream, (int)launches.size()));
+        for (size_t l = 0; l < launches.size(); ++l) {
+            const Launch &L = launches[l];
+            hipStream_t s = fork.stream((int)l);
+            if (L.store == kStoreGlobal) PYHEA_HIP(launch_pad_fill(ddev + L.first, L.count, s));
+            PYHEA_HIP(launch_mc(ddev + L.first, L.count, L.store, L.M, L.S, L.B, L.H, L.lds, INT_MAX, s));
+            if (L.store == kStoreGlobal) PYHEA_HIP(launch_pad_drain(ddev + L.first, L.count, s));
+        }
+        PYHEA_HIP(fork.end());
     }
 
-    // results: states, maintained counts, and a fresh recount of the final configuration
-    for (int c = 0; c < n; ++c) {
-        const pyhea_status s = count_configs(jobs[c].g, 1, jobs[c].species_dev, (int32_t *)(base + slot[c].recount),
-                                             (int32_t *)(base + slot[c].bad), stream);
-        if (s != PYHEA_OK) return s;
-    }
-    std::vector<ChainState> sts(n);
-    std::vector<std::vector<int32_t>> rec32(n);
-    for (int c = 0; c < n; ++c) {
-        PYHEA_HIP(hipMemcpyAsync(&sts[c], base + slot[c].state, sizeof(ChainState), hipMemcpyDeviceToHost, stream));
-        PYHEA_HIP(hipMemcpyAsync(cnt32[c].data(), base + slot[c].counts, cnt32[c].size() * 4,
-                                 hipMemcpyDeviceToHost, stream));
-        rec32[c].resize(cnt32[c].size());
-        PYHEA_HIP(hipMemcpyAsync(rec32[c].data(), base + slot[c].recount, rec32[c].size() * 4,
-                                 hipMemcpyDeviceToHost, stream));
-    }
+    // results: states, maintained counts, and a fresh recount of every final configuration
+    PYHEA_HIP(launch_count_tasks(tasks + n, tile0, n, n_tiles, stream));
+    PYHEA_HIP(hipMemcpyAsync(hx.data(), base, x_end, hipMemcpyDeviceToHost, stream));
     PYHEA_HIP(hipStreamSynchronize(stream));
+    const int32_t *cnt = (const int32_t *)(hx.data() + o_counts);
+    const int32_t *rec = (const int32_t *)(hx.data() + o_recount);
+    const ChainState *sts = (const ChainState *)(hx.data() + o_state);
     if (final_counts) final_counts->assign(n, {});
     for (int c = 0; c < n; ++c) {
         const Geometry &g = jobs[c].g;
-        if (rec32[c] != cnt32[c]) {
+        if (!std::equal(cnt + eoff[c], cnt + eoff[c + 1], rec + eoff[c])) {
             set_error("chain " + std::to_string(c) + ": maintained pair counts differ from a recount");
             return PYHEA_EDEVICE;
         }
-        std::vector<int64_t> c64(rec32[c].begin(), rec32[c].end());
+        std::vector<int64_t> c64(rec + eoff[c], rec + eoff[c + 1]);
         pyhea_mc_stats &s = stats[c];
         std::memset(&s, 0, sizeof(s));
         s.trials = sts[c].trials;

@@ -42,6 +42,43 @@ int64_t now_ns() {
 
 enum JobPhase { kQueued, kResident, kDone, kCancelled, kFailed };
 
+// One device allocation per resident job:
+//   small block: counts | recount | bad | bad2 | state | R | target
+//   species (N bytes), then the padded HBM copy for jobs that keep it in HBM.
+struct JobLayout {
+    size_t counts, recount, bad, bad2, state, R, target, small_end, species, pad, total;
+};
+
+JobLayout job_layout(const Geometry &g, int store) {
+    const size_t E = (size_t)g.S * g.M * g.M;
+    JobLayout l;
+    size_t off = 0;
+    l.counts = off;
+    off += E * 4;
+    l.recount = off;
+    off += E * 4;
+    l.bad = off;
+    off += 4;
+    l.bad2 = off;
+    off += 4;
+    off = (off + 7) & ~size_t(7);
+    l.state = off;
+    off += sizeof(ChainState);
+    l.R = off;
+    off += E * 8;
+    l.target = off;
+    off += E * 8;
+    l.small_end = off;
+    off = (off + 255) & ~size_t(255);
+    l.species = off;
+    off += (size_t)g.N;
+    off = (off + 255) & ~size_t(255);
+    l.pad = off;
+    if (store == kStoreGlobal) off += (size_t)g.Npad;
+    l.total = (off + 255) & ~size_t(255);
+    return l;
+}
+
 struct Job {
     uint64_t id = 0;
     Geometry g;
@@ -60,11 +97,10 @@ struct Job {
     int store = kStoreLds8;
     int lds = 0;
     int H = 1;
-    size_t off_counts = 0, off_recount = 0, off_bad = 0, off_R = 0, off_t = 0, off_state = 0,
-           off_species = 0, off_pad = 0;
+    JobLayout lay{};
 };
 
-size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
+int64_t job_footprint(const Geometry &g, int store) { return (int64_t)job_layout(g, store).total; }
 
 struct Server {
     int device = 0;
@@ -81,63 +117,22 @@ struct Server {
     int64_t n_submitted = 0, n_admitted = 0, n_finished = 0, n_rejected = 0, n_rounds = 0;
     int64_t bytes_resident = 0;
     std::vector<hipStream_t> streams;
-    void *desc_dev = nullptr;
+    // device tables sized for max_slots: the round's descriptors, their gathered
+    // states, and (for admission and retirement) descriptors and count tasks
+    void *desc_dev = nullptr, *state_dev = nullptr, *aux_desc_dev = nullptr, *task_dev = nullptr;
     int lds_budget = 0;
     std::string worker_error;
 
     void run();
-    bool admit(Job *j, hipStream_t s);
-    void retire(Job *j, hipStream_t s);
-    void release(Job *j);
+    // admits `js` (device memory, uploads, initial counts); returns per job success
+    std::vector<bool> admit(const std::vector<Job *> &js, hipStream_t s);
+    void retire(const std::vector<Job *> &js, hipStream_t s);
+    void release(Job *j, hipStream_t s);
 };
 
-int64_t job_footprint(const Geometry &g, int store) {
-    const int64_t E = (int64_t)g.S * g.M * g.M;
-    int64_t b = 0;
-    b += a256(E * 4) * 2 + a256(4) + a256(E * 8) * 2 + a256(sizeof(ChainState));
-    b += a256((size_t)g.N);
-    if (store == kStoreGlobal) b += a256((size_t)g.Npad);
-    return b;
-}
-
-bool Server::admit(Job *j, hipStream_t s) {
+void fill_desc(Job *j) {
     const Geometry &g = j->g;
-    const size_t E = (size_t)g.S * g.M * g.M;
-    size_t off = 0;
-    j->off_counts = off;
-    off = a256(off + E * 4);
-    j->off_recount = off;
-    off = a256(off + E * 4);
-    j->off_bad = off;
-    off = a256(off + 4);
-    j->off_R = off;
-    off = a256(off + E * 8);
-    j->off_t = off;
-    off = a256(off + E * 8);
-    j->off_state = off;
-    off = a256(off + sizeof(ChainState));
-    j->off_species = off;
-    off = a256(off + (size_t)g.N);
-    j->off_pad = off;
-    if (j->store == kStoreGlobal) off = a256(off + (size_t)g.Npad);
-    if (hipMalloc(&j->mem, off) != hipSuccess) {
-        j->mem = nullptr;
-        return false;
-    }
     char *base = (char *)j->mem;
-    // n_i from the host copy (same integers the counts give), then R
-    int64_t n[kMaxSpecies] = {0};
-    for (int8_t v : j->species) n[v]++;
-    std::vector<double> R(E);
-    ratio_table(g, n, R.data());
-    ChainState st0;
-    std::memset(&st0, 0, sizeof(st0));
-    bool ok = hipMemcpyAsync(base + j->off_species, j->species.data(), g.N, hipMemcpyHostToDevice, s) == hipSuccess;
-    ok = ok && hipMemcpyAsync(base + j->off_R, R.data(), E * 8, hipMemcpyHostToDevice, s) == hipSuccess;
-    ok = ok && hipMemcpyAsync(base + j->off_t, j->target.data(), E * 8, hipMemcpyHostToDevice, s) == hipSuccess;
-    ok = ok && hipMemcpyAsync(base + j->off_state, &st0, sizeof(st0), hipMemcpyHostToDevice, s) == hipSuccess;
-    ok = ok && count_configs(g, 1, (const int8_t *)(base + j->off_species), (int32_t *)(base + j->off_counts),
-                             (int32_t *)(base + j->off_bad), s) == PYHEA_OK;
     ChainDesc &d = j->desc;
     std::memset(&d, 0, sizeof(d));
     fill_chain_geometry(g, &d);
@@ -149,72 +144,143 @@ bool Server::admit(Job *j, hipStream_t s) {
     d.depth_limit = j->params.depth_limit;
     d.tau = j->params.accept_tol;
     for (int k = 0; k < kMaxShells; ++k) d.w[k] = k < g.S ? j->weight[k] : 0.0;
-    d.species = (int8_t *)(base + j->off_species);
-    d.pad_global = j->store == kStoreGlobal ? (int8_t *)(base + j->off_pad) : nullptr;
-    d.R = (const double *)(base + j->off_R);
-    d.target = (const double *)(base + j->off_t);
-    d.counts = (int32_t *)(base + j->off_counts);
+    d.species = (int8_t *)(base + j->lay.species);
+    d.pad_global = j->store == kStoreGlobal ? (int8_t *)(base + j->lay.pad) : nullptr;
+    d.R = (const double *)(base + j->lay.R);
+    d.target = (const double *)(base + j->lay.target);
+    d.counts = (int32_t *)(base + j->lay.counts);
     d.log = nullptr;
     d.log_cap = 0;
-    d.state = (ChainState *)(base + j->off_state);
+    d.state = (ChainState *)(base + j->lay.state);
     d.store = j->store;
     d.lds_bytes = j->lds;
-    if (ok && j->store == kStoreGlobal) {
-        // one-chain descriptor copy for the padding kernel
-        void *tmp = nullptr;
-        ok = hipMalloc(&tmp, sizeof(ChainDesc)) == hipSuccess;
-        ok = ok && hipMemcpyAsync(tmp, &d, sizeof(d), hipMemcpyHostToDevice, s) == hipSuccess;
-        ok = ok && launch_pad_fill((const ChainDesc *)tmp, 1, s) == hipSuccess;
-        ok = ok && hipStreamSynchronize(s) == hipSuccess;
-        if (tmp) (void)hipFree(tmp);
+}
+
+CountTask count_task(const Job *j, bool recount) {
+    CountTask t;
+    fill_eval_desc(j->g, &t.ed);
+    char *base = (char *)j->mem;
+    t.species = (const int8_t *)(base + j->lay.species);
+    t.counts = (int32_t *)(base + (recount ? j->lay.recount : j->lay.counts));
+    t.bad = (int32_t *)(base + (recount ? j->lay.bad2 : j->lay.bad));
+    return t;
+}
+
+// Pair counts of the given jobs' configurations in one launch.
+bool count_jobs(const std::vector<Job *> &js, bool recount, void *task_dev, hipStream_t s) {
+    if (js.empty()) return true;
+    const size_t n = js.size();
+    std::vector<char> host(n * sizeof(CountTask) + n * 4);
+    CountTask *t = (CountTask *)host.data();
+    uint32_t *t0 = (uint32_t *)(host.data() + n * sizeof(CountTask));
+    uint32_t tiles = 0;
+    for (size_t i = 0; i < n; ++i) {
+        t[i] = count_task(js[i], recount);
+        t0[i] = tiles;
+        tiles += count_tiles((uint32_t)js[i]->g.N);
     }
-    ok = ok && hipStreamSynchronize(s) == hipSuccess;
+    bool ok = hipMemcpyAsync(task_dev, host.data(), host.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    ok = ok && launch_count_tasks((const CountTask *)task_dev,
+                                  (const uint32_t *)((char *)task_dev + n * sizeof(CountTask)), (int)n, tiles,
+                                  s) == hipSuccess;
     return ok;
 }
 
-void Server::retire(Job *j, hipStream_t s) {
-    const Geometry &g = j->g;
-    char *base = (char *)j->mem;
-    const size_t E = (size_t)g.S * g.M * g.M;
-    bool ok = true;
-    if (j->store == kStoreGlobal) {
-        void *tmp = nullptr;
-        ok = hipMalloc(&tmp, sizeof(ChainDesc)) == hipSuccess;
-        ok = ok && hipMemcpyAsync(tmp, &j->desc, sizeof(ChainDesc), hipMemcpyHostToDevice, s) == hipSuccess;
-        ok = ok && launch_pad_drain((const ChainDesc *)tmp, 1, s) == hipSuccess;
-        ok = ok && hipStreamSynchronize(s) == hipSuccess;
-        if (tmp) (void)hipFree(tmp);
+std::vector<bool> Server::admit(const std::vector<Job *> &js, hipStream_t s) {
+    std::vector<bool> good(js.size(), false);
+    std::vector<Job *> live;
+    std::vector<ChainDesc> pads;
+    for (size_t i = 0; i < js.size(); ++i) {
+        Job *j = js[i];
+        const Geometry &g = j->g;
+        j->lay = job_layout(g, j->store);
+        if (hipMallocAsync(&j->mem, j->lay.total, s) != hipSuccess) {
+            j->mem = nullptr;
+            continue;
+        }
+        char *base = (char *)j->mem;
+        // zeroed counts, flags and state, then R (n_i from the host copy) and the target
+        const size_t E = (size_t)g.S * g.M * g.M;
+        std::vector<char> small(j->lay.small_end, 0);
+        int64_t n[kMaxSpecies] = {0};
+        for (int8_t v : j->species) n[v]++;
+        ratio_table(g, n, (double *)(small.data() + j->lay.R));
+        std::memcpy(small.data() + j->lay.target, j->target.data(), E * 8);
+        // host memory is pageable, so both copies complete before they return
+        bool ok = hipMemcpyAsync(base, small.data(), small.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+        ok = ok && hipMemcpyAsync(base + j->lay.species, j->species.data(), g.N, hipMemcpyHostToDevice, s) ==
+                       hipSuccess;
+        if (!ok) {
+            (void)hipFreeAsync(j->mem, s);
+            j->mem = nullptr;
+            continue;
+        }
+        fill_desc(j);
+        if (j->store == kStoreGlobal) pads.push_back(j->desc);
+        live.push_back(j);
+        good[i] = true;
     }
-    ok = ok && count_configs(g, 1, (const int8_t *)(base + j->off_species), (int32_t *)(base + j->off_recount),
-                             (int32_t *)(base + j->off_bad), s) == PYHEA_OK;
-    ChainState st;
-    std::vector<int32_t> cm(E), cr(E);
-    ok = ok && hipMemcpyAsync(&st, base + j->off_state, sizeof(st), hipMemcpyDeviceToHost, s) == hipSuccess;
-    ok = ok && hipMemcpyAsync(cm.data(), base + j->off_counts, E * 4, hipMemcpyDeviceToHost, s) == hipSuccess;
-    ok = ok && hipMemcpyAsync(cr.data(), base + j->off_recount, E * 4, hipMemcpyDeviceToHost, s) == hipSuccess;
-    ok = ok && hipMemcpyAsync(j->species.data(), base + j->off_species, g.N, hipMemcpyDeviceToHost, s) == hipSuccess;
+    bool ok = count_jobs(live, false, task_dev, s);
+    if (ok && !pads.empty()) {
+        ok = hipMemcpyAsync(aux_desc_dev, pads.data(), pads.size() * sizeof(ChainDesc), hipMemcpyHostToDevice, s) ==
+             hipSuccess;
+        ok = ok && launch_pad_fill((const ChainDesc *)aux_desc_dev, (int)pads.size(), s) == hipSuccess;
+    }
     ok = ok && hipStreamSynchronize(s) == hipSuccess;
-    std::memset(&j->stats, 0, sizeof(j->stats));
-    if (!ok || cm != cr) {
-        j->status = PYHEA_EDEVICE;
-    } else {
-        std::vector<int64_t> c64(cr.begin(), cr.end());
-        double SF[2];
-        host_objective(g, c64.data(), j->target.data(), j->weight.data(), nullptr, SF);
-        j->stats.trials = st.trials;
-        j->stats.null_trials = st.null_trials;
-        j->stats.commits = st.commits;
-        j->stats.steps = st.steps;
-        j->stats.stop_reason = st.stop_reason;
-        j->stats.S = SF[0];
-        j->stats.F = SF[1];
-        j->stats.status = PYHEA_OK;
-    }
-    j->stats.status = j->status;
+    if (!ok) std::fill(good.begin(), good.end(), false);
+    return good;
 }
 
-void Server::release(Job *j) {
-    if (j->mem) (void)hipFree(j->mem);
+void Server::retire(const std::vector<Job *> &js, hipStream_t s) {
+    if (js.empty()) return;
+    std::vector<ChainDesc> pads;
+    for (Job *j : js)
+        if (j->store == kStoreGlobal) pads.push_back(j->desc);
+    bool ok = true;
+    if (!pads.empty()) {
+        ok = hipMemcpyAsync(aux_desc_dev, pads.data(), pads.size() * sizeof(ChainDesc), hipMemcpyHostToDevice, s) ==
+             hipSuccess;
+        ok = ok && launch_pad_drain((const ChainDesc *)aux_desc_dev, (int)pads.size(), s) == hipSuccess;
+    }
+    ok = ok && count_jobs(js, true, task_dev, s);
+    std::vector<std::vector<char>> small(js.size());
+    for (size_t i = 0; ok && i < js.size(); ++i) {
+        Job *j = js[i];
+        small[i].resize(j->lay.R);  // counts, recount, flags, state
+        ok = hipMemcpyAsync(small[i].data(), j->mem, small[i].size(), hipMemcpyDeviceToHost, s) == hipSuccess;
+        ok = ok && hipMemcpyAsync(j->species.data(), (char *)j->mem + j->lay.species, j->g.N,
+                                  hipMemcpyDeviceToHost, s) == hipSuccess;
+    }
+    ok = ok && hipStreamSynchronize(s) == hipSuccess;
+    for (size_t i = 0; i < js.size(); ++i) {
+        Job *j = js[i];
+        std::memset(&j->stats, 0, sizeof(j->stats));
+        const Geometry &g = j->g;
+        const size_t E = (size_t)g.S * g.M * g.M;
+        const int32_t *cm = ok ? (const int32_t *)(small[i].data() + j->lay.counts) : nullptr;
+        const int32_t *cr = ok ? (const int32_t *)(small[i].data() + j->lay.recount) : nullptr;
+        if (!ok || !std::equal(cm, cm + E, cr)) {
+            j->status = PYHEA_EDEVICE;
+        } else {
+            ChainState st;
+            std::memcpy(&st, small[i].data() + j->lay.state, sizeof(st));
+            std::vector<int64_t> c64(cr, cr + E);
+            double SF[2];
+            host_objective(g, c64.data(), j->target.data(), j->weight.data(), nullptr, SF);
+            j->stats.trials = st.trials;
+            j->stats.null_trials = st.null_trials;
+            j->stats.commits = st.commits;
+            j->stats.steps = st.steps;
+            j->stats.stop_reason = st.stop_reason;
+            j->stats.S = SF[0];
+            j->stats.F = SF[1];
+        }
+        j->stats.status = j->status;
+    }
+}
+
+void Server::release(Job *j, hipStream_t s) {
+    if (j->mem) (void)hipFreeAsync(j->mem, s);
     j->mem = nullptr;
     bytes_resident -= j->footprint;
 }
@@ -250,22 +316,26 @@ void Server::run() {
                 continue;
             }
         }
-        for (Job *j : to_admit) {
-            const bool ok = admit(j, s0);
+        if (!to_admit.empty()) {
+            const std::vector<bool> good = admit(to_admit, s0);
             std::lock_guard<std::mutex> lk(mu);
-            if (!ok) {
-                release(j);
-                j->status = PYHEA_ENOMEM;
-                j->phase = kFailed;
-                j->t_finish = now_ns();
-                ++n_finished;
-                cv_done.notify_all();
-                continue;
+            const int64_t t = now_ns();
+            for (size_t i = 0; i < to_admit.size(); ++i) {
+                Job *j = to_admit[i];
+                if (!good[i]) {
+                    release(j, s0);
+                    j->status = PYHEA_ENOMEM;
+                    j->phase = kFailed;
+                    j->t_finish = t;
+                    ++n_finished;
+                    continue;
+                }
+                j->phase = kResident;
+                j->t_admit = t;
+                resident.push_back(j);
+                ++n_admitted;
             }
-            j->phase = kResident;
-            j->t_admit = now_ns();
-            resident.push_back(j);
-            ++n_admitted;
+            cv_done.notify_all();
         }
         std::vector<Job *> run_set;
         {
@@ -283,36 +353,45 @@ void Server::run() {
         for (Job *j : run_set)
             groups[{j->store, j->g.M, j->g.S, j->params.cand_per_step, j->H}].push_back(j);
         std::vector<ChainDesc> descs;
+        std::vector<Job *> order;
         std::vector<std::pair<size_t, std::vector<Job *>>> launches;
         for (auto &kv : groups) {
             launches.push_back({descs.size(), kv.second});
-            for (Job *j : kv.second) descs.push_back(j->desc);
+            for (Job *j : kv.second) {
+                descs.push_back(j->desc);
+                order.push_back(j);
+            }
         }
         bool ok = hipMemcpyAsync(desc_dev, descs.data(), descs.size() * sizeof(ChainDesc), hipMemcpyHostToDevice,
                                  s0) == hipSuccess;
-        ok = ok && hipStreamSynchronize(s0) == hipSuccess;
+        hipEvent_t ready = nullptr;
+        ok = ok && hipEventCreateWithFlags(&ready, hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipEventRecord(ready, s0) == hipSuccess;
         for (size_t gi = 0; ok && gi < launches.size(); ++gi) {
             auto &L = launches[gi];
             const Job *j0 = L.second[0];
             int lds = 0;
             for (Job *j : L.second) lds = std::max(lds, j->lds);
-            hipStream_t s = streams[gi % streams.size()];
-            ok = launch_mc((const ChainDesc *)desc_dev + L.first, (int)L.second.size(), j0->store, j0->g.M,
-                           j0->g.S, j0->params.cand_per_step, j0->H, lds, steps_per_round, s) == hipSuccess;
+            hipStream_t s = streams[1 + gi % (streams.size() - 1)];
+            ok = hipStreamWaitEvent(s, ready, 0) == hipSuccess;
+            ok = ok && launch_mc((const ChainDesc *)desc_dev + L.first, (int)L.second.size(), j0->store, j0->g.M,
+                                 j0->g.S, j0->params.cand_per_step, j0->H, lds, steps_per_round, s) == hipSuccess;
         }
-        for (hipStream_t s : streams) ok = ok && hipStreamSynchronize(s) == hipSuccess;
-        // done flags
-        states.resize(run_set.size());
-        for (size_t i = 0; ok && i < run_set.size(); ++i)
-            ok = hipMemcpyAsync(&states[i], run_set[i]->desc.state, sizeof(ChainState), hipMemcpyDeviceToHost, s0) ==
-                 hipSuccess;
+        for (size_t i = 1; i < streams.size(); ++i) ok = ok && hipStreamSynchronize(streams[i]) == hipSuccess;
+        if (ready) (void)hipEventDestroy(ready);
+        // every job's state in one read-back
+        states.resize(order.size());
+        ok = ok && launch_gather_states((const ChainDesc *)desc_dev, (int)order.size(), (ChainState *)state_dev,
+                                        s0) == hipSuccess;
+        ok = ok && hipMemcpyAsync(states.data(), state_dev, order.size() * sizeof(ChainState), hipMemcpyDeviceToHost,
+                                  s0) == hipSuccess;
         ok = ok && hipStreamSynchronize(s0) == hipSuccess;
         std::vector<Job *> finished, cancelled;
         {
             std::lock_guard<std::mutex> lk(mu);
             ++n_rounds;
-            for (size_t i = 0; i < run_set.size(); ++i) {
-                Job *j = run_set[i];
+            for (size_t i = 0; i < order.size(); ++i) {
+                Job *j = order[i];
                 if (!ok) {
                     j->status = PYHEA_EDEVICE;
                     finished.push_back(j);
@@ -323,23 +402,26 @@ void Server::run() {
                 }
             }
         }
+        std::vector<Job *> good;
         for (Job *j : finished)
-            if (j->status == PYHEA_OK) retire(j, s0);
+            if (j->status == PYHEA_OK) good.push_back(j);
+        retire(good, s0);
         {
             std::lock_guard<std::mutex> lk(mu);
+            const int64_t t = now_ns();
             for (Job *j : finished) {
                 j->phase = j->status == PYHEA_OK ? kDone : kFailed;
                 j->stats.status = j->status;
-                j->t_finish = now_ns();
-                release(j);
+                j->t_finish = t;
+                release(j, s0);
                 resident.erase(std::find(resident.begin(), resident.end(), j));
                 ++n_finished;
             }
             for (Job *j : cancelled) {
-                release(j);
+                release(j, s0);
                 j->phase = kCancelled;
                 j->status = PYHEA_ECANCELLED;
-                j->t_finish = now_ns();
+                j->t_finish = t;
                 resident.erase(std::find(resident.begin(), resident.end(), j));
                 ++n_finished;
             }
@@ -367,7 +449,7 @@ pyhea_status pyhea_serve_open(int64_t hbm_budget_bytes, int32_t max_slots, int32
     s->max_slots = max_slots;
     s->steps_per_round = steps_per_round > 0 ? steps_per_round : 256;
     s->lds_budget = max_lds_per_block();
-    s->streams.resize(4);
+    s->streams.resize(4);  // [0]: admission, retirement and read-back; [1..3]: the rounds' launches
     for (auto &st : s->streams) {
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
             delete s;
@@ -375,10 +457,16 @@ pyhea_status pyhea_serve_open(int64_t hbm_budget_bytes, int32_t max_slots, int32
             return PYHEA_EDEVICE;
         }
     }
-    if (hipMalloc(&s->desc_dev, sizeof(ChainDesc) * (size_t)max_slots) != hipSuccess) {
+    const size_t slots = (size_t)max_slots;
+    if (hipMalloc(&s->desc_dev, sizeof(ChainDesc) * slots) != hipSuccess ||
+        hipMalloc(&s->state_dev, sizeof(ChainState) * slots) != hipSuccess ||
+        hipMalloc(&s->aux_desc_dev, sizeof(ChainDesc) * slots) != hipSuccess ||
+        hipMalloc(&s->task_dev, (sizeof(CountTask) + 4) * slots) != hipSuccess) {
+        for (void *p : {s->desc_dev, s->state_dev, s->aux_desc_dev, s->task_dev})
+            if (p) (void)hipFree(p);
         for (auto st : s->streams) (void)hipStreamDestroy(st);
         delete s;
-        set_error("serve_open: descriptor table allocation failed");
+        set_error("serve_open: table allocation failed");
         return PYHEA_ENOMEM;
     }
     s->worker = std::thread([s] { s->run(); });
@@ -546,10 +634,12 @@ pyhea_status pyhea_serve_close(void *server) {
     if (s->worker.joinable()) s->worker.join();
     (void)hipSetDevice(s->device);
     for (Job *j : s->resident) {
-        if (j->mem) (void)hipFree(j->mem);
+        if (j->mem) (void)hipFreeAsync(j->mem, s->streams[0]);
         j->mem = nullptr;
     }
-    if (s->desc_dev) (void)hipFree(s->desc_dev);
+    (void)hipStreamSynchronize(s->streams[0]);
+    for (void *p : {s->desc_dev, s->state_dev, s->aux_desc_dev, s->task_dev})
+        if (p) (void)hipFree(p);
     for (auto st : s->streams) (void)hipStreamDestroy(st);
     delete s;
     return PYHEA_OK;

@@ -103,6 +103,56 @@ __global__ void __launch_bounds__(256) count_gather_kernel(EvalDesc ed, int64_t 
     }
 }
 
+// The same gather count for many configurations of different geometries: the
+// grid is the concatenation of every configuration's site tiles.
+__global__ void __launch_bounds__(256) count_tasks_kernel(const CountTask *__restrict__ tasks,
+                                                          const uint32_t *__restrict__ tile0, int n) {
+    __shared__ int32_t hist[kMaxShells * kMaxSpecies * kMaxSpecies];
+    __shared__ int32_t bad_sh;
+    // owning configuration: the last c with tile0[c] <= blockIdx.x
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile0[mid] <= blockIdx.x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const CountTask &t = tasks[lo];
+    const EvalDesc &ed = t.ed;
+    const int M = ed.M, E = ed.S * ed.M * ed.M;
+    for (int e = threadIdx.x; e < E; e += blockDim.x) hist[e] = 0;
+    if (threadIdx.x == 0) bad_sh = 0;
+    __syncthreads();
+    const int8_t *sp = t.species;
+    const uint32_t p0 = (blockIdx.x - tile0[lo]) * (uint32_t)kCountTile;
+    const uint32_t p1 = min(p0 + (uint32_t)kCountTile, ed.N);
+    for (uint32_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const int s = sp[p];
+        if (s < 0 || s >= M) {
+            bad_sh = 1;
+            continue;
+        }
+        const SiteCoord c = site_coord(p, ed.lgA, ed.Lx, ed.Ly, ed.inv_Lx, ed.inv_Ly);
+        for (int hh = 0; hh < ed.n_half; ++hh) {
+            const int8_t *o = ed.half[c.b][hh];
+            const int x = wrap1(c.cx + o[0], ed.Lx);
+            const int y = wrap1(c.cy + o[1], ed.Ly);
+            const int z = wrap1(c.cz + o[2], ed.Lz);
+            const int s2 = sp[((z * ed.Ly + y) * ed.Lx + x) * ed.A + o[3]];
+            if (s2 < 0 || s2 >= M) continue;
+            atomicAdd(&hist[(o[4] * M + s) * M + s2], 1);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+        const int kk = e / (M * M), i = (e / M) % M, j = e % M;
+        const int v = hist[e] + hist[(kk * M + j) * M + i];
+        if (v) atomicAdd(&t.counts[e], v);
+    }
+    if (threadIdx.x == 0 && bad_sh) atomicOr(t.bad, 1);
+}
+
 __global__ void zero_i32_kernel(int32_t *p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0;
@@ -269,6 +319,13 @@ hipError_t launch_count_gather(const EvalDesc &ed, int64_t K, const int8_t *spec
     const int gy = (int)std::min<int64_t>(K, 65535);
     hipLaunchKernelGGL(count_gather_kernel, dim3(per_cfg, gy), dim3(256), 0, stream, ed, K, species,
                        counts, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_tasks(const CountTask *tasks, const uint32_t *tile0, int n, uint32_t n_tiles,
+                              hipStream_t stream) {
+    if (n <= 0 || n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(count_tasks_kernel, dim3(n_tiles), dim3(256), 0, stream, tasks, tile0, n);
     return hipGetLastError();
 }
 

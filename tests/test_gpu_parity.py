@@ -249,3 +249,23 @@ def test_mc_batch_equals_each_chain_alone():
         np.testing.assert_array_equal(fin[offsets[i]:offsets[i + 1]], sp_o)
         np.testing.assert_array_equal(logs[i * logcap:i * logcap + stats[i]["log_len"]], log_o)
         assert stats[i]["S"] == st_o["S"] and stats[i]["commits"] == st_o["commits"]
+
+
+@pytest.mark.parametrize("defect", ["out_of_range", "absent_species"])
+def test_mc_batch_rejects_bad_chain(defect):
+    chains = wl.config4(n_chains=6, seed=12, n_trials=500)
+    species = np.concatenate([c.species for c in chains])
+    offsets = np.concatenate([[0], np.cumsum([c.N for c in chains])])
+    bad = species.copy()
+    lo, hi = offsets[3], offsets[4]
+    if defect == "out_of_range":
+        bad[lo + 7] = chains[3].M
+    else:
+        bad[lo:hi] = np.where(bad[lo:hi] == 0, 1, bad[lo:hi])
+    d = dev(bad)
+    probs = [(c.lattice, c.L, c.M, c.S, c.target, c.weight) for c in chains]
+    pars = [pb.make_params(c.seed, c.chain_id, c.n_trials, c.B) for c in chains]
+    with pytest.raises(pb.PyheaError) as e:
+        pb.pyhea_mc_batch(probs, d, offsets, pars)
+    assert "chain 3" in str(e.value)
+    np.testing.assert_array_equal(d.cpu().numpy(), bad)   # nothing ran
