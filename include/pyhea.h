@@ -231,15 +231,29 @@ pyhea_status pyhea_serve_close(void *server);
 pyhea_status pyhea_philox4x32_10(const uint32_t *ctr_dev, uint64_t seed, int64_t n,
                                  uint32_t *out_dev, void *stream);
 
-/* Autotuner: file that caches tuned launch shapes (NULL = no persistence), and
- * a switch to force one shape (-1 = tuned).  Shapes never change results. */
-pyhea_status pyhea_tune_set_cache(const char *path);
+/* Launch shape of the MC kernels.  The library picks it by rule from the
+ * chain's size and the number of chains launched together: where the
+ * configuration lives (LDS bytes when they fit, else LDS nibbles, else HBM),
+ * one wavefront per shell, and the steps per pass.  This switch forces one
+ * shape family process-wide: -1 = automatic, 0 = automatic, 1 = LDS nibbles
+ * (else HBM), 2 = HBM, 3 = automatic, 4 = offsets spread evenly over the
+ * shell wavefronts.  Shapes never change results; EINVAL outside -1..4. */
 pyhea_status pyhea_tune_force(int32_t variant);
 
 /* Full-evaluation kernel: -1 = automatic (bit-sliced where it covers the
  * geometry, else gather), 0 = gather, 1 = bit-sliced where possible.  Both
  * give identical counts. */
 pyhea_status pyhea_tune_force_eval(int32_t kernel);
+
+/* Steps whose candidates one pass of the MC kernel evaluates at once: 0 =
+ * automatic (the largest value up to 8 whose block still lets every chain of
+ * the call, or every slot of a server, be resident on the GPU at once), or
+ * 1..8 (capped so that a block has at most 16 wavefronts).  Candidates are drawn from counters, not from the state, so the
+ * candidates of later steps can be evaluated against the current state; a
+ * step's evaluation is used only if every earlier step of the pass committed
+ * nothing (the state is then unchanged).  Trajectories are bit-identical for
+ * every value.  Process-wide; EINVAL outside 0..8. */
+pyhea_status pyhea_tune_force_lookahead(int32_t steps);
 
 #ifdef __cplusplus
 }

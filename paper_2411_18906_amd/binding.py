@@ -24,8 +24,8 @@ EXPORTS = [
     "pyhea_version", "pyhea_last_error", "pyhea_sro_eval", "pyhea_sro_eval_batch",
     "pyhea_trial_eval", "pyhea_mc_run", "pyhea_mc_batch", "pyhea_serve_open",
     "pyhea_serve_submit", "pyhea_serve_poll", "pyhea_serve_cancel", "pyhea_serve_counters",
-    "pyhea_serve_close", "pyhea_philox4x32_10", "pyhea_tune_set_cache", "pyhea_tune_force",
-    "pyhea_tune_force_eval",
+    "pyhea_serve_close", "pyhea_philox4x32_10", "pyhea_tune_force",
+    "pyhea_tune_force_eval", "pyhea_tune_force_lookahead",
 ]
 
 
@@ -87,9 +87,9 @@ def lib():
             "pyhea_serve_counters": ([P, P], i32),
             "pyhea_serve_close": ([P], i32),
             "pyhea_philox4x32_10": ([P, u64, i64, P, P], i32),
-            "pyhea_tune_set_cache": ([ctypes.c_char_p], i32),
             "pyhea_tune_force": ([i32], i32),
             "pyhea_tune_force_eval": ([i32], i32),
+            "pyhea_tune_force_lookahead": ([i32], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -245,8 +245,8 @@ def pyhea_tune_force_eval(kernel: int):
     _check(lib().pyhea_tune_force_eval(kernel))
 
 
-def pyhea_tune_set_cache(path: str | None):
-    _check(lib().pyhea_tune_set_cache(None if path is None else path.encode()))
+def pyhea_tune_force_lookahead(steps: int):
+    _check(lib().pyhea_tune_force_lookahead(steps))
 
 
 class Server:

@@ -273,17 +273,21 @@ pyhea_status pyhea_philox4x32_10(const uint32_t *ctr_dev, uint64_t seed, int64_t
     return guard(PYHEA_OK);
 }
 
-pyhea_status pyhea_tune_set_cache(const char *path) {
-    set_tune_cache_path(path);
-    return guard(PYHEA_OK);
-}
-
 pyhea_status pyhea_tune_force_eval(int32_t kernel) {
     if (kernel < -1 || kernel > 1) {
         set_error("kernel must be -1 (automatic), 0 (gather) or 1 (bit-sliced)");
         return PYHEA_EINVAL;
     }
     set_forced_eval_kernel(kernel);
+    return guard(PYHEA_OK);
+}
+
+pyhea_status pyhea_tune_force_lookahead(int32_t steps) {
+    if (steps < 0 || steps > kMaxLookahead) {
+        set_error("steps per pass must be 0 (automatic) or 1..8");
+        return PYHEA_EINVAL;
+    }
+    set_forced_lookahead(steps);
     return guard(PYHEA_OK);
 }
 

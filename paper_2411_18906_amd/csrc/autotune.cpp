@@ -1,6 +1,7 @@
 // Launch-shape tuning for the MC kernels (see autotune.h).
 #include "autotune.h"
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 
@@ -12,31 +13,46 @@ namespace {
 std::mutex g_mu;
 int g_forced = -1;
 int g_forced_eval = -1;
-std::string g_cache;
+int g_forced_lookahead = 0;
 }  // namespace
 
-LaunchShape choose_launch(const Geometry &g, int B, int lds_budget, int variant) {
-    LaunchShape ls;
-    const int fixed1 = mc_lds_bytes(g.S, g.M, B, 1);
-    const int64_t b8 = fixed1 + species_store_bytes(kStoreLds8, g.Npad);
-    const int64_t b4 = fixed1 + species_store_bytes(kStoreLds4, g.Npad);
+int wave_budget(int n_chains) {
+    // every chain of a launch should be resident at once: 256 CUs x 16 wavefronts
+    const int n = n_chains < 1 ? 1 : n_chains;
+    return n <= 256 ? 16 : (4096 / n < 1 ? 1 : 4096 / n);
+}
+
+LaunchShape choose_launch(const Geometry &g, int B, int lds_budget, int variant, int n_chains) {
+    int stores[3], ns = 0;
     if (variant == 2) {
-        ls.store = kStoreGlobal;
+        stores[ns++] = kStoreGlobal;
     } else if (variant == 1) {
-        ls.store = b4 <= lds_budget ? kStoreLds4 : kStoreGlobal;
+        stores[ns++] = kStoreLds4;
+        stores[ns++] = kStoreGlobal;
     } else {
-        ls.store = b8 <= lds_budget ? kStoreLds8 : (b4 <= lds_budget ? kStoreLds4 : kStoreGlobal);
+        stores[ns++] = kStoreLds8;
+        stores[ns++] = kStoreLds4;
+        stores[ns++] = kStoreGlobal;
     }
-    ls.H = 1;
-    ls.lds = (int)(fixed1 + species_store_bytes(ls.store, g.Npad));
-    if (variant != 3 && mc_halves(g.S, B) == 2) {
-        const int64_t l2 = mc_lds_bytes(g.S, g.M, B, 2) + species_store_bytes(ls.store, g.Npad);
-        if (l2 <= lds_budget) {
-            ls.H = 2;
-            ls.lds = (int)l2;
+    const int Gs = (B + 63) / 64;
+    const int fk = forced_lookahead();
+    const int budget = std::max(fk > 0 ? 16 : wave_budget(n_chains), g.S * Gs);
+    // one wavefront per shell (gathering its own shell, or with variant 4 an
+    // equal share of all offsets), then as many steps per pass as the block allows
+    const int W = g.S;
+    const int bal = variant == 4 && g.S > 1 ? 1 : 0;
+    const int kmax = fk > 0 ? fk : std::max(1, std::min(kMaxLookahead, budget / (W * Gs)));
+    for (int si = 0; si < ns; ++si)
+        for (int K = kmax; K >= 1; --K) {
+            if (mc_block_waves(B, W, K) > 16) continue;
+            for (int bl : {bal, 0}) {
+                const int64_t lds = mc_lds_bytes(g.S, g.M, B, W, bl, K) + species_store_bytes(stores[si], g.Npad);
+                if (lds <= lds_budget) return LaunchShape{stores[si], W, bl, K, (int)lds};
+                if (bal == 0) break;
+            }
         }
-    }
-    return ls;
+    // the HBM store with one step per pass
+    return LaunchShape{kStoreGlobal, W, 0, 1, mc_lds_bytes(g.S, g.M, B, W, 0, 1)};
 }
 
 int forced_variant() {
@@ -59,14 +75,15 @@ void set_forced_eval_kernel(int v) {
     g_forced_eval = v;
 }
 
-const char *tune_cache_path() {
+int forced_lookahead() {
     std::lock_guard<std::mutex> lk(g_mu);
-    return g_cache.c_str();
+    return g_forced_lookahead;
 }
 
-void set_tune_cache_path(const char *p) {
+void set_forced_lookahead(int k) {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_cache = p ? p : "";
+    g_forced_lookahead = k;
 }
+
 
 }  // namespace pyhea

@@ -8,20 +8,29 @@
 namespace pyhea {
 
 // Launch shape of one chain: where its configuration lives (LDS bytes, LDS
-// nibbles or HBM) and how many wavefronts share each shell (H = 1 or 2).
+// nibbles or HBM), the wavefronts per slot group (W) and whether the offsets
+// are spread evenly over them (bal), and how many steps one pass evaluates
+// (K, 1..kMaxLookahead).
 struct LaunchShape {
     int store;
-    int H;
+    int W;
+    int bal;
+    int K;
     int lds;
 };
 
 // Variants: 0 = automatic (LDS bytes when they fit, else nibbles, else HBM;
-// two wavefronts per shell when the block and LDS allow); 1 = LDS nibbles when
-// they fit, else HBM; 2 = always HBM; 3 = automatic store, one wavefront per
-// shell.  Every variant gives bit-identical results.
-constexpr int kNumStoreVariants = 4;
+// each wavefront gathers its own shell's offsets); 1 = LDS nibbles when they
+// fit, else HBM; 2 = always HBM; 3 = the automatic shape (kept as an explicit
+// name); 4 = automatic store, every wavefront of a slot group gathers an equal
+// share of all offsets and the shells' partial histograms meet in LDS.  The block size follows the
+// number of chains launched together (n_chains) so that all can be resident;
+// the steps per pass are the largest (up to 4) that fit it, unless forced.
+// Every variant gives bit-identical results.
+constexpr int kNumStoreVariants = 5;
 
-LaunchShape choose_launch(const Geometry &g, int B, int lds_budget, int variant);
+LaunchShape choose_launch(const Geometry &g, int B, int lds_budget, int variant, int n_chains);
+int wave_budget(int n_chains);
 
 // Variant forced through pyhea_tune_force (-1 = none).
 int forced_variant();
@@ -30,7 +39,8 @@ void set_forced_variant(int v);
 // 0 = gather, 1 = bit-sliced).
 int forced_eval_kernel();
 void set_forced_eval_kernel(int v);
-const char *tune_cache_path();
-void set_tune_cache_path(const char *p);
+// Steps per pass forced through pyhea_tune_force_lookahead (0 = automatic).
+int forced_lookahead();
+void set_forced_lookahead(int k);
 
 }  // namespace pyhea

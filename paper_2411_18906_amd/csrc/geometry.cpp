@@ -192,4 +192,14 @@ void fill_chain_geometry(const Geometry &g, ChainDesc *d) {
     }
 }
 
+int symmetric_target(const double *t, int S, int M) {
+    for (int k = 0; k < S; ++k)
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < i; ++j) {
+                const double a = t[(k * M + i) * M + j], b = t[(k * M + j) * M + i];
+                if (std::memcmp(&a, &b, sizeof(double)) != 0) return 0;
+            }
+    return 1;
+}
+
 }  // namespace pyhea

@@ -111,7 +111,11 @@ struct ChainDesc {
     ChainState *state;
     int32_t store;
     int32_t lds_bytes;     // LDS needed by this chain
+    int32_t sym;           // 1 if target[k][i][j] == target[k][j][i] bit for bit
 };
+
+// 1 if a [S][M][M] target table equals its transpose bit for bit.
+int symmetric_target(const double *t, int S, int M);
 
 // Fills the geometry part of a ChainDesc.
 void fill_chain_geometry(const Geometry &g, ChainDesc *d);

@@ -8,17 +8,21 @@
 namespace pyhea {
 
 // LDS layout of the MC kernel (must match the carve order in mc_kernels.hip).
-__host__ __device__ inline int mc_lds_bytes(int S, int M, int B, int H = 1) {
+// W = wavefronts per slot group (>= S), bal = offsets spread evenly over them
+// (partial histograms exchanged through LDS), K = steps whose candidates one
+// pass evaluates (records for K * B slots).
+__host__ __device__ inline int mc_lds_bytes(int S, int M, int B, int W = 0, int bal = 0, int K = 1) {
     auto r = [](int b) { return (b + 15) & ~15; };
     const int E = S * M * M;
+    const int Bt = K * B;
     int n = 0;
     n += r(E * 32);                               // entry records
     n += r(kMaxOffsets * 16) + r(kMaxOffsets * 4);     // dlin4, offmod
-    n += r(B * 8) + 5 * r(B * 4);                 // rec_dS, p, q, pp, pq, ab
-    n += 3 * r(S * B * 8);                        // rec_cp, rec_cq, rec_dQ
-    n += 2 * r(B * 4);                            // order, list
-    n += r(2 * kMaxShells * 8) + r(16 * 4);       // sh_dQ (two buffers), sh_int
-    if (H == 2) n += r(2 * 2 * S * B * 8) + r(S * B * 4 * 8);  // partial histograms, row sums
+    n += r(Bt * 8) + 5 * r(Bt * 4);               // rec_dS, p, q, pp, pq, ab
+    n += 3 * r(S * Bt * 8);                       // rec_cp, rec_cq, rec_dQ
+    n += 2 * r(Bt * 4);                           // order, list (per step of a pass)
+    n += r(2 * kMaxShells * 8) + r(32 * 4);       // sh_dQ (two buffers), sh_int
+    if (bal) n += r(S * W * 2 * Bt * (M > 6 ? 8 : 4));  // partial histograms
     return n;
 }
 
@@ -29,12 +33,14 @@ inline int64_t species_store_bytes(int store, int64_t Npad) {
     return 0;
 }
 
-int mc_block_threads(int S, int B, int H);
+// Wavefronts of one chain's block: K steps x slot groups x W.
+inline int mc_block_waves(int B, int W, int K) { return K * ((B + 63) / 64) * W; }
+int mc_block_threads(int B, int W, int K);
+constexpr int kMaxLookahead = 8;
 
-// Halves per shell: 2 when the block stays within 1024 threads.
-inline int mc_halves(int S, int B) { return ((B + 63) / 64) * S * 2 <= 16 ? 2 : 1; }
-hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M, int S, int B, int H,
-                     int lds_bytes, int max_steps, hipStream_t stream);
+// One launch of n_chains chains (one block each) for up to max_steps steps.
+hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M, int S, int B, int W, int bal,
+                     int K, int lds_bytes, int max_steps, hipStream_t stream);
 hipError_t launch_pad_fill(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);
 hipError_t launch_pad_drain(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);
 // out[i] = *descs_dev[i].state (device array of n_chains states).

@@ -80,8 +80,7 @@ struct Lds {
     int32_t *list;      // [B]
     double *sh_dQ;      // [2][kMaxShells]
     int32_t *sh_int;    // scalars
-    uint64_t *part;     // [S][2 halves][2 (cp, cq)][B] partial histograms (H == 2)
-    double *rowbuf;     // [S][B][4] row sums of the second half (H == 2)
+    void *part;         // [S][W][2 (cp, cq)][K B] partial histograms (bal)
     uint8_t *store;     // species store
 };
 
@@ -186,7 +185,7 @@ __device__ __forceinline__ int sel4(int4 v, int b) {
 
 template <int kStore, int M>
 __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ descs,
-                                                  int32_t max_steps, int32_t H) {
+                                                  int32_t max_steps, int32_t W, int32_t bal, int32_t K) {
     using Hist = typename HistT<(M > 6)>::type;
     const ChainDesc &d = descs[blockIdx.x];
     ChainState *st = d.state;
@@ -194,13 +193,19 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
 
     const int S = d.S, E = S * M * M;
     const int B = d.B;
+    const int Gs = (B + kWave - 1) / kWave;  // slot groups per step
+    const int Bt = K * B;                    // records: K consecutive steps of B slots
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    const int hh = wave % H;          // half of the shell's work (H = 1 or 2)
-    const int k = (wave / H) % S;     // shell handled by this wave
-    const int grp = wave / (S * H);   // slot group
-    const int slot = grp * kWave + lane;
-    const bool lead = hh == 0;        // the wave that owns the slot's records
+    // a slot group has W >= S wavefronts; wavefront k < S owns shell k.  With
+    // bal, wavefront w gathers offsets [Z w / W, Z (w + 1) / W) of all Z offsets
+    // (ordered by shell); without, W == S and wavefront k gathers shell k.
+    const int grp = wave / W;         // slot group
+    const int widx = wave - grp * W;  // wavefront within the group
+    const int k = widx < S ? widx : -1;  // shell owned (-1: gathers only)
+    const int kw = grp / Gs;          // step offset of this wave's slots
+    const int slot = (grp - kw * Gs) * kWave + lane;  // candidate within its step
+    const int rix = kw * B + slot;    // its record (when slot < B)
     const int nthreads = blockDim.x;
 
     extern __shared__ __align__(16) uint8_t smem[];
@@ -210,23 +215,20 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
         L.ent = (Ent *)carve(p, E * sizeof(Ent));
         L.dlin4 = (int4 *)carve(p, kMaxOffsets * 16);
         L.offmod = (int32_t *)carve(p, kMaxOffsets * 4);
-        L.rec_dS = (double *)carve(p, B * 8);
-        L.rec_p = (uint32_t *)carve(p, B * 4);
-        L.rec_q = (uint32_t *)carve(p, B * 4);
-        L.rec_pp = (uint32_t *)carve(p, B * 4);
-        L.rec_pq = (uint32_t *)carve(p, B * 4);
-        L.rec_ab = (uint32_t *)carve(p, B * 4);
-        L.rec_cp = (uint64_t *)carve(p, S * B * 8);
-        L.rec_cq = (uint64_t *)carve(p, S * B * 8);
-        L.rec_dQ = (double *)carve(p, S * B * 8);
-        L.order = (int32_t *)carve(p, B * 4);
-        L.list = (int32_t *)carve(p, B * 4);
+        L.rec_dS = (double *)carve(p, Bt * 8);
+        L.rec_p = (uint32_t *)carve(p, Bt * 4);
+        L.rec_q = (uint32_t *)carve(p, Bt * 4);
+        L.rec_pp = (uint32_t *)carve(p, Bt * 4);
+        L.rec_pq = (uint32_t *)carve(p, Bt * 4);
+        L.rec_ab = (uint32_t *)carve(p, Bt * 4);
+        L.rec_cp = (uint64_t *)carve(p, S * Bt * 8);
+        L.rec_cq = (uint64_t *)carve(p, S * Bt * 8);
+        L.rec_dQ = (double *)carve(p, S * Bt * 8);
+        L.order = (int32_t *)carve(p, Bt * 4);
+        L.list = (int32_t *)carve(p, Bt * 4);
         L.sh_dQ = (double *)carve(p, 2 * kMaxShells * 8);
-        L.sh_int = (int32_t *)carve(p, 16 * 4);
-        if (H == 2) {
-            L.part = (uint64_t *)carve(p, 2 * 2 * S * B * 8);
-            L.rowbuf = (double *)carve(p, S * B * 4 * 8);
-        }
+        L.sh_int = (int32_t *)carve(p, 32 * 4);
+        if (bal) L.part = carve(p, S * W * 2 * Bt * (int)sizeof(Hist));
         L.store = p;
     }
 
@@ -282,34 +284,43 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
     const uint32_t key0 = (uint32_t)d.seed, key1 = (uint32_t)(d.seed >> 32);
     const int h = d.halo;
     // this wave's offsets and rows of shell k
-    const int zsk = d.zstart[k], zek = d.zstart[k + 1];
-    const int zmid = zsk + (zek - zsk) / 2;
-    const int zs = H == 2 ? (lead ? zsk : zmid) : zsk;
-    const int ze = H == 2 ? (lead ? zmid : zek) : zek;
-    constexpr int RH = M / 2;
-    const int r0 = H == 2 ? (lead ? 0 : RH) : 0;
-    const int r1 = H == 2 ? (lead ? RH : M) : M;
-    const int G = (B + kWave - 1) / kWave;
+    const int Z = d.zstart[S];
+    const int zsk = k >= 0 ? d.zstart[k] : 0, zek = k >= 0 ? d.zstart[k + 1] : 0;
+    const int g0 = bal ? (Z * widx) / W : zsk;
+    const int g1 = bal ? (Z * (widx + 1)) / W : zek;
     if (trials >= d.n_trials) done = true;
     double wk[kMaxShells];
 #pragma unroll
     for (int kk = 0; kk < kMaxShells; ++kk) wk[kk] = d.w[kk];
     const double tau = d.tau;
 
-    for (int it = 0; it < max_steps && !done; ++it) {
-        const int64_t left = d.n_trials - trials;
-        const int tasks = left < B ? (int)left : B;
+    // A pass evaluates the candidates of up to K consecutive steps against the
+    // current state.  Steps are then taken in order; a step whose candidates
+    // include no improving swap commits nothing and leaves the state as it was,
+    // so the next step's evaluation is still exact.  The first step that commits
+    // ends the pass.  After a pass whose first step committed, the next pass
+    // evaluates one step.
+    int kpref = K;
+    int64_t steps_run = 0;
+    while (!done && steps_run < max_steps) {
+        const int ke = (int)min((int64_t)kpref, (int64_t)max_steps - steps_run);
 
-        // ---- phase 1: draw and evaluate (slot, shell k) ----------------------------
+        // ---- phase 1: draw and evaluate (step offset kw, slot) --------------------------
+        // Each wavefront gathers the neighbours along its offsets [g0, g1) into one
+        // histogram pair per shell; shell k's owner (wavefront k of the group) adds
+        // the pairs of every wavefront whose offsets meet shell k (exact integer
+        // sums) and evaluates dQ_k.
         {
-            const bool active = slot < tasks;
+            const int64_t left = d.n_trials - trials - (int64_t)kw * B;
+            const int tasks_w = left <= 0 ? 0 : (left < B ? (int)left : B);
+            const bool active = kw < ke && slot < tasks_w;
             uint32_t p = 0, q = 0, ppos = 0, qpos = 0;
             int a = 0, b = 0;
             bool live = false;
-            Hist cp = 0, cq = 0;
+            Hist cp = 0, cq = 0;   // the owner's full shell-k histograms
             double dQ = 0.0;
             if (active) {
-                uint32_t c[4] = {(uint32_t)slot, (uint32_t)step, d.chain_id, 0u};
+                uint32_t c[4] = {(uint32_t)slot, (uint32_t)(step + kw), d.chain_id, 0u};
                 philox4x32_10(c, key0, key1);
                 p = __umulhi(c[0], d.N);
                 q = __umulhi(c[1], d.N);
@@ -326,55 +337,68 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                 b = load_species<kStore>(L, d, pidq);
                 live = (a != b);
                 if (live) {
-                    // neighbour species, 6 offsets at a time: all loads issued before use
-                    constexpr int kU = 6;
-                    int t = zs;
 #pragma unroll 1
-                    for (; t + kU <= ze; t += kU) {
-                        int4 dl[kU];
-#pragma unroll
-                        for (int u = 0; u < kU; ++u) dl[u] = L.dlin4[t + u];
-                        int ap[kU], aq[kU];
-#pragma unroll
-                        for (int u = 0; u < kU; ++u) {
-                            ap[u] = pidp + sel4(dl[u], sp.b);
-                            aq[u] = pidq + sel4(dl[u], sq.b);
-                        }
-                        int vp[kU], vq[kU];
-#pragma unroll
-                        for (int u = 0; u < kU; ++u) {
-                            vp[u] = load_species<kStore>(L, d, ap[u]);
-                            vq[u] = load_species<kStore>(L, d, aq[u]);
-                        }
-#pragma unroll
-                        for (int u = 0; u < kU; ++u) {
-                            cp += one_at<Hist>(vp[u]);
-                            cq += one_at<Hist>(vq[u]);
-                        }
-                    }
+                    for (int s2 = 0; s2 < S; ++s2) {
+                        const int t0 = max(g0, (int)d.zstart[s2]), t1 = min(g1, (int)d.zstart[s2 + 1]);
+                        if (t0 >= t1) continue;
+                        Hist hp = 0, hq = 0;
+                        // 4 offsets at a time: all loads issued before use
+                        constexpr int kU = 4;
+                        int t = t0;
 #pragma unroll 1
-                    for (; t < ze; ++t) {
-                        const int4 dl = L.dlin4[t];
-                        cp += one_at<Hist>(load_species<kStore>(L, d, pidp + sel4(dl, sp.b)));
-                        cq += one_at<Hist>(load_species<kStore>(L, d, pidq + sel4(dl, sq.b)));
+                        for (; t + kU <= t1; t += kU) {
+                            int4 dl[kU];
+#pragma unroll
+                            for (int u = 0; u < kU; ++u) dl[u] = L.dlin4[t + u];
+                            int ap[kU], aq[kU];
+#pragma unroll
+                            for (int u = 0; u < kU; ++u) {
+                                ap[u] = pidp + sel4(dl[u], sp.b);
+                                aq[u] = pidq + sel4(dl[u], sq.b);
+                            }
+                            int vp[kU], vq[kU];
+#pragma unroll
+                            for (int u = 0; u < kU; ++u) {
+                                vp[u] = load_species<kStore>(L, d, ap[u]);
+                                vq[u] = load_species<kStore>(L, d, aq[u]);
+                            }
+#pragma unroll
+                            for (int u = 0; u < kU; ++u) {
+                                hp += one_at<Hist>(vp[u]);
+                                hq += one_at<Hist>(vq[u]);
+                            }
+                        }
+#pragma unroll 1
+                        for (; t < t1; ++t) {
+                            const int4 dl = L.dlin4[t];
+                            hp += one_at<Hist>(load_species<kStore>(L, d, pidp + sel4(dl, sp.b)));
+                            hq += one_at<Hist>(load_species<kStore>(L, d, pidq + sel4(dl, sq.b)));
+                        }
+                        if (bal) {
+                            // this wavefront's part of shell s2 (read by its owner when live)
+                            Hist *pt = (Hist *)L.part + ((s2 * W + widx) * 2) * Bt;
+                            pt[rix] = hp;
+                            pt[Bt + rix] = hq;
+                        } else {
+                            cp = hp;   // the wavefront's own shell
+                            cq = hq;
+                        }
                     }
                 }
             }
-            if (H == 2) {
-                // exchange the two halves' partial histograms (exact integer sums)
-                uint64_t *mine = L.part + ((k * 2 + hh) * 2) * B;
-                const uint64_t *other = L.part + ((k * 2 + (1 - hh)) * 2) * B;
-                if (slot < B) {
-                    mine[slot] = (uint64_t)cp;
-                    mine[B + slot] = (uint64_t)cq;
-                }
+            if (bal) {
                 __syncthreads();
-                if (live) {
-                    cp += (Hist)other[slot];
-                    cq += (Hist)other[B + slot];
+                if (k >= 0 && live) {
+                    for (int w2 = 0; w2 < W; ++w2) {
+                        const int a0 = (Z * w2) / W, a1 = (Z * (w2 + 1)) / W;
+                        if (max(a0, zsk) >= min(a1, zek)) continue;
+                        const Hist *pt = (const Hist *)L.part + ((k * W + w2) * 2) * Bt;
+                        cp += pt[rix];
+                        cq += pt[Bt + rix];
+                    }
                 }
             }
-            if (live) {
+            if (k >= 0 && live) {
                 // remove the partner: q is reached from p along m shell-k offsets
                 int m;
                 if (!d.small_cell) {
@@ -393,67 +417,87 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                     D[j] = fld(cq, j) - fld(cp, j);
                     u[j] = (j == a ? 1 : 0) - (j == b ? 1 : 0);
                 }
-                // dQ_k = sum over rows i of (sum over j of sq(N + dN) - sq(N)); this wave
-                // takes rows [r0, r1)
-                const Ent *row = L.ent + k * M * M;
-#pragma unroll
-                for (int i = 0; i < M; ++i) {
-                    if (i < r0 || i >= r1) continue;
-                    double rs = 0.0;
+                // dQ_k = sum over rows i of (sum over j of sq(N + dN) - sq(N))
+                if (d.sym) {
+                    // Symmetric N, dN, R and target: only rows lo = min(a, b) and
+                    // hi = max(a, b) need evaluating; row i of the others holds
+                    // nonzero terms only at columns lo < hi, equal to entries
+                    // (lo, i) and (hi, i).  Terms with dN = 0 are exactly +0.0.
+                    const int lo = a < b ? a : b, hi = a < b ? b : a;
+                    const int ulo = lo == a ? 1 : -1;
+                    const int Dlo = fld(cq, lo) - fld(cp, lo), Dhi = fld(cq, hi) - fld(cp, hi);
+                    const Ent *elo = L.ent + (k * M + lo) * M, *ehi = L.ent + (k * M + hi) * M;
+                    double ro[M];   // row j's sum when j is neither lo nor hi
+                    double rlo = 0.0, rhi = 0.0;
 #pragma unroll
                     for (int j = 0; j < M; ++j) {
-                        const Ent en = row[i * M + j];
-                        const int dn = __mul24(u[i], D[j]) + __mul24(u[j], D[i]);
-                        const double sn = sq_dev(en.cnt + dn, en.R, en.t);
-                        rs = rs + (sn - en.sq);
+                        const Ent e1 = elo[j];
+                        const int n1 = __mul24(ulo, D[j]) + __mul24(u[j], Dlo);
+                        const double dl = sq_dev(e1.cnt + n1, e1.R, e1.t) - e1.sq;
+                        const Ent e2 = ehi[j];
+                        const int n2 = __mul24(-ulo, D[j]) + __mul24(u[j], Dhi);
+                        const double dh = sq_dev(e2.cnt + n2, e2.R, e2.t) - e2.sq;
+                        rlo = rlo + dl;
+                        rhi = rhi + dh;
+                        ro[j] = dl + dh;
                     }
-                    if (lead)
-                        dQ = dQ + rs;
-                    else
-                        L.rowbuf[(k * B + slot) * 4 + (i - RH)] = rs;
-                }
-            }
-            if (H == 2) {
-                __syncthreads();
-                if (lead && live) {
 #pragma unroll
-                    for (int i = RH; i < M; ++i) dQ = dQ + L.rowbuf[(k * B + slot) * 4 + (i - RH)];
+                    for (int i = 0; i < M; ++i) dQ = dQ + (i == lo ? rlo : (i == hi ? rhi : ro[i]));
+                } else {
+                    const Ent *row = L.ent + k * M * M;
+#pragma unroll
+                    for (int i = 0; i < M; ++i) {
+                        double rs = 0.0;
+#pragma unroll
+                        for (int j = 0; j < M; ++j) {
+                            const Ent en = row[i * M + j];
+                            const int dn = __mul24(u[i], D[j]) + __mul24(u[j], D[i]);
+                            const double sn = sq_dev(en.cnt + dn, en.R, en.t);
+                            rs = rs + (sn - en.sq);
+                        }
+                        dQ = dQ + rs;
+                    }
                 }
             }
-            if (lead && slot < B) {
-                L.rec_cp[k * B + slot] = (uint64_t)cp;
-                L.rec_cq[k * B + slot] = (uint64_t)cq;
-                L.rec_dQ[k * B + slot] = dQ;
+            if (k >= 0 && slot < B && kw < ke) {
+                L.rec_cp[k * Bt + rix] = (uint64_t)cp;
+                L.rec_cq[k * Bt + rix] = (uint64_t)cq;
+                L.rec_dQ[k * Bt + rix] = dQ;
                 if (k == 0) {
-                    L.rec_p[slot] = p;
-                    L.rec_q[slot] = q;
-                    L.rec_pp[slot] = ppos;
-                    L.rec_pq[slot] = qpos;
-                    L.rec_ab[slot] = (uint32_t)a | ((uint32_t)b << 8) |
-                                     ((uint32_t)(active && !live) << 16) | ((uint32_t)active << 17);
+                    L.rec_p[rix] = p;
+                    L.rec_q[rix] = q;
+                    L.rec_pp[rix] = ppos;
+                    L.rec_pq[rix] = qpos;
+                    L.rec_ab[rix] = (uint32_t)a | ((uint32_t)b << 8) |
+                                    ((uint32_t)(active && !live) << 16) | ((uint32_t)active << 17);
                 }
             }
         }
         __syncthreads();
 
-        // ---- phase 2: dS per slot, compaction and ranking (wave 0) -------------------
-        if (wave == 0) {
+        // ---- phase 2: per step of the pass (its first wavefront, steps side by
+        // side): dS per slot, nulls, improving slots ranked by (dS, slot) -----------
+        if (grp % Gs == 0 && wave == grp * W && kw < ke) {
+            const int kk = kw;
+            int32_t *ord = L.order + kk * B;
+            int32_t *lst = L.list + kk * B;
             int n_impr = 0;
             int step_nulls = 0;
             double my_dS = 0.0;
             uint64_t imp_mask = 0;
-            for (int g = 0; g < G; ++g) {
+            for (int g = 0; g < Gs; ++g) {
                 const int s = g * kWave + lane;
+                const int r = kk * B + s;
                 bool imp = false;
                 if (s < B) {
-                    const uint32_t ab = L.rec_ab[s];
+                    const uint32_t ab = L.rec_ab[r];
                     const bool act = (ab >> 17) & 1u, nul = (ab >> 16) & 1u;
                     double dS = 0.0;
 #pragma unroll
-                    for (int kk = 0; kk < kMaxShells; ++kk)
-                        if (kk < S) dS = dS + wk[kk] * L.rec_dQ[kk * B + s];
-                    L.rec_dS[s] = dS;
-                    if (G == 1) my_dS = dS;
+                    for (int q = 0; q < kMaxShells; ++q)
+                        if (q < S) dS = dS + wk[q] * L.rec_dQ[q * Bt + r];
+                    L.rec_dS[r] = dS;
+                    my_dS = dS;
                     imp = act && !nul && (dS < -tau);
                     step_nulls += (int)__popcll(ballot64(act && nul));
                 } else {
@@ -461,38 +505,71 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                 }
                 const uint64_t mask = ballot64(imp);
                 const int before = (int)__popcll(mask & ((1ull << lane) - 1ull));
-                if (imp) L.list[n_impr + before] = s;
+                if (imp) lst[n_impr + before] = s;
                 n_impr += (int)__popcll(mask);
                 imp_mask = mask;
             }
-            if (G == 1) {
-                // rank by (dS, slot) with the improving slots' dS read across lanes
-                int rank = 0;
-                for (uint64_t m = imp_mask; m; m &= m - 1) {
-                    const int l = __ffsll((long long)m) - 1;
-                    const double d2 = readlane_f64(my_dS, l);
-                    rank += (d2 < my_dS || (d2 == my_dS && l < lane)) ? 1 : 0;
-                }
-                if ((imp_mask >> lane) & 1ull) L.order[rank] = lane;
-            } else {
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_s_waitcnt(0);
-                for (int idx = lane; idx < n_impr; idx += kWave) {
-                    const int s = L.list[idx];
-                    const double ds = L.rec_dS[s];
+            if (n_impr > 0) {
+                if (Gs == 1) {
+                    // rank with the improving slots' dS read across lanes
                     int rank = 0;
-                    for (int j = 0; j < n_impr; ++j) {
-                        const int s2 = L.list[j];
-                        const double d2 = L.rec_dS[s2];
-                        rank += (d2 < ds || (d2 == ds && s2 < s)) ? 1 : 0;
+                    for (uint64_t m = imp_mask; m; m &= m - 1) {
+                        const int l = __ffsll((long long)m) - 1;
+                        const double d2 = readlane_f64(my_dS, l);
+                        rank += (d2 < my_dS || (d2 == my_dS && l < lane)) ? 1 : 0;
                     }
-                    L.order[rank] = s;
+                    if ((imp_mask >> lane) & 1ull) ord[rank] = lane;
+                } else {
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_s_waitcnt(0);
+                    for (int idx = lane; idx < n_impr; idx += kWave) {
+                        const int s = lst[idx];
+                        const double ds = L.rec_dS[kk * B + s];
+                        int rank = 0;
+                        for (int j = 0; j < n_impr; ++j) {
+                            const int s2 = lst[j];
+                            const double d2 = L.rec_dS[kk * B + s2];
+                            rank += (d2 < ds || (d2 == ds && s2 < s)) ? 1 : 0;
+                        }
+                        ord[rank] = s;
+                    }
                 }
             }
-            if (lane == 0) L.sh_int[0] = n_impr;
-            nulls += step_nulls;  // only thread 0's copy is stored
+            if (lane == 0) {
+                L.sh_int[4 + kk] = step_nulls;
+                L.sh_int[12 + kk] = n_impr;
+            }
         }
         __syncthreads();
+        int kstar = ke;
+        for (int kk = ke - 1; kk >= 0; --kk)
+            if (L.sh_int[12 + kk] > 0) kstar = kk;
+        const int n_impr = kstar < ke ? L.sh_int[12 + kstar] : 0;
+        int pass_steps = 0;
+        // steps of the pass before kstar commit nothing
+        for (int kk = 0; kk < kstar && !done; ++kk) {
+            const int64_t left = d.n_trials - trials;
+            trials += left < B ? left : B;
+            nulls += L.sh_int[4 + kk];
+            ++step;
+            ++depth;
+            ++pass_steps;
+            if (d.depth_limit > 0 && depth >= d.depth_limit) {
+                stop_reason = PYHEA_STOP_DEPTH;
+                done = true;
+            } else if (trials >= d.n_trials) {
+                stop_reason = PYHEA_STOP_TRIALS;
+                done = true;
+            }
+        }
+        if (done || kstar >= ke) {
+            steps_run += pass_steps;
+            kpref = K;
+            __syncthreads();
+            continue;
+        }
+        const int rb = kstar * B;   // records of the committing step
+        const int tasks = (int)min((int64_t)B, d.n_trials - trials);
 
         // ---- phase 3: commits ---------------------------------------------------------
         // Candidates in rank order.  A candidate within shells 1..S of an earlier
@@ -503,17 +580,16 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
         // decisions; shell k's entries belong to one wave, and the waves meet once
         // per re-validated candidate to add the shells' dQ.  Site writes wait
         // until the end of the phase: later candidates never read committed sites.
-        const int n_impr = L.sh_int[0];
         int n_commit = 0;
         int n_meet = 0;
         uint32_t cpr[kMaxB / 32];
 #pragma unroll
         for (int r = 0; r < kMaxB / 32; ++r) cpr[r] = 0;
-        const bool ewave = grp == 0 && lead;   // one wave per shell handles its entries
+        const bool ewave = grp == 0 && k >= 0;   // one wave per shell handles its entries
         for (int u = 0; u < n_impr; ++u) {
             if (d.mode == PYHEA_MODE_BEST && n_commit > 0) break;
-            const int s = L.order[u];
-            const uint32_t upp = L.rec_pp[s], upq = L.rec_pq[s];
+            const int s = L.order[rb + u];
+            const uint32_t upp = L.rec_pp[rb + s], upq = L.rec_pq[rb + s];
             bool hit = false;
 #pragma unroll
             for (int r = 0; r < kMaxB / 32; ++r) {
@@ -522,13 +598,13 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                     hit |= near_or_equal(d, upp, cpr[r]) || near_or_equal(d, upq, cpr[r]);
             }
             if (ballot64(hit) != 0) continue;
-            const uint32_t ab = L.rec_ab[s];
+            const uint32_t ab = L.rec_ab[rb + s];
             const int a = (int)(ab & 0xFFu), b = (int)((ab >> 8) & 0xFFu);
             // this wave's shell-k change of entry e = lane (the S entry waves only)
             int dn = 0;
             int e = 0;
             if (ewave && lane < M * M) {
-                const Hist cp = (Hist)L.rec_cp[k * B + s], cq = (Hist)L.rec_cq[k * B + s];
+                const Hist cp = (Hist)L.rec_cp[k * Bt + rb + s], cq = (Hist)L.rec_cq[k * Bt + rb + s];
                 const int i = lane / M, j = lane - (lane / M) * M;
                 const int ui = (i == a ? 1 : 0) - (i == b ? 1 : 0), uj = (j == a ? 1 : 0) - (j == b ? 1 : 0);
                 dn = __mul24(ui, fld(cq, j) - fld(cp, j)) + __mul24(uj, fld(cq, i) - fld(cp, i));
@@ -590,8 +666,8 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
         for (int t = threadIdx.x; t < n_commit * 2; t += nthreads) {
             const int s = L.list[t >> 1];
             const int side = t & 1;
-            const uint32_t ab = L.rec_ab[s];
-            const uint32_t site = side ? L.rec_q[s] : L.rec_p[s];
+            const uint32_t ab = L.rec_ab[rb + s];
+            const uint32_t site = side ? L.rec_q[rb + s] : L.rec_p[rb + s];
             const int v = side ? (int)(ab & 0xFFu) : (int)((ab >> 8) & 0xFFu);
             const SiteCoord sc = site_coord(site, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
             write_site<kStore>(L, d, sc.cx, sc.cy, sc.cz, sc.b, v);
@@ -604,16 +680,18 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                     uint32_t *rec = d.log + 4 * at;
                     rec[0] = (uint32_t)step;
                     rec[1] = (uint32_t)s;
-                    rec[2] = L.rec_p[s];
-                    rec[3] = L.rec_q[s];
+                    rec[2] = L.rec_p[rb + s];
+                    rec[3] = L.rec_q[rb + s];
                 }
             }
         }
         commits += n_commit;
 
-        // ---- phase 4: bookkeeping --------------------------------------------------
+        // ---- phase 4: bookkeeping of the committing step ----------------------------
         trials += tasks;
+        nulls += L.sh_int[4 + kstar];
         ++step;
+        ++pass_steps;
         depth = n_commit > 0 ? 0 : depth + 1;
         if (d.depth_limit > 0 && depth >= d.depth_limit) {
             stop_reason = PYHEA_STOP_DEPTH;
@@ -622,6 +700,8 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
             stop_reason = PYHEA_STOP_TRIALS;
             done = true;
         }
+        steps_run += pass_steps;
+        kpref = kstar == 0 ? 1 : K;
         __syncthreads();
     }
 
@@ -677,7 +757,7 @@ __global__ void pad_drain_kernel(const ChainDesc *__restrict__ descs) {
 
 }  // namespace
 
-int mc_block_threads(int S, int B, int H) { return ((B + kWave - 1) / kWave) * S * H * kWave; }
+int mc_block_threads(int B, int W, int K) { return mc_block_waves(B, W, K) * kWave; }
 
 template <int kStore>
 const void *mc_fn(int M) {
@@ -692,15 +772,17 @@ const void *mc_fn(int M) {
     }
 }
 
-hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M, int S, int B, int H,
-                     int lds_bytes, int max_steps, hipStream_t stream) {
-    const dim3 grid(n_chains), block(mc_block_threads(S, B, H));
+hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M, int S, int B, int W, int bal,
+                     int K, int lds_bytes, int max_steps, hipStream_t stream) {
+    if (mc_block_threads(B, W, K) > 1024 || K < 1 || K > kMaxLookahead || W < S || (!bal && W != S))
+        return hipErrorInvalidValue;
+    const dim3 grid(n_chains), block(mc_block_threads(B, W, K));
     const void *fn = store == kStoreLds8 ? mc_fn<kStoreLds8>(M)
                      : store == kStoreLds4 ? mc_fn<kStoreLds4>(M)
                                            : mc_fn<kStoreGlobal>(M);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
-    void *args[] = {(void *)&descs_dev, (void *)&max_steps, (void *)&H};
+    void *args[] = {(void *)&descs_dev, (void *)&max_steps, (void *)&W, (void *)&bal, (void *)&K};
     return hipLaunchKernel(fn, grid, block, args, (size_t)lds_bytes, stream);
 }
 

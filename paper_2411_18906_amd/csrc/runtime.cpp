@@ -275,7 +275,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
     std::vector<LaunchShape> shape(n);
     std::vector<size_t> o_pad(n, 0);
     for (int c = 0; c < n; ++c) {
-        shape[c] = choose_launch(jobs[c].g, jobs[c].params.cand_per_step, lds_budget, variant < 0 ? 0 : variant);
+        shape[c] = choose_launch(jobs[c].g, jobs[c].params.cand_per_step, lds_budget, variant < 0 ? 0 : variant, n);
         if (shape[c].store == kStoreGlobal) {
             off = align256(off);
             o_pad[c] = off;
@@ -292,7 +292,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
     for (int c = 0; c < n; ++c)
         std::memcpy(hy_at(o_target) + eoff[c] * 8, jobs[c].target.data(), jobs[c].target.size() * 8);
     std::vector<ChainDesc> descs(n);
-    std::map<std::tuple<int, int, int, int, int>, std::vector<int>> groups;
+    std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<int>> groups;
     for (int c = 0; c < n; ++c) {
         const ChainJob &j = jobs[c];
         ChainDesc &d = descs[c];
@@ -316,10 +316,11 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         d.state = (ChainState *)(base + o_state) + c;
         d.store = shape[c].store;
         d.lds_bytes = shape[c].lds;
-        groups[{shape[c].store, j.g.M, j.g.S, d.B, shape[c].H}].push_back(c);
+        d.sym = symmetric_target(j.target.data(), j.g.S, j.g.M);
+        groups[{shape[c].store, j.g.M, j.g.S, d.B, shape[c].W, shape[c].bal, shape[c].K}].push_back(c);
     }
     struct Launch {
-        int first, count, store, M, S, B, H, lds;
+        int first, count, store, M, S, B, W, bal, K, lds;
     };
     std::vector<Launch> launches;
     {
@@ -331,8 +332,16 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
             std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
                 return jobs[a].params.n_trials > jobs[b].params.n_trials;
             });
-            Launch L{at, (int)idx.size(), std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                     std::get<3>(kv.first), std::get<4>(kv.first), 0};
+            Launch L{at,
+                     (int)idx.size(),
+                     std::get<0>(kv.first),
+                     std::get<1>(kv.first),
+                     std::get<2>(kv.first),
+                     std::get<3>(kv.first),
+                     std::get<4>(kv.first),
+                     std::get<5>(kv.first),
+                     std::get<6>(kv.first),
+                     0};
             for (int c : idx) {
                 L.lds = std::max(L.lds, descs[c].lds_bytes);
                 hd[at++] = descs[c];
@@ -396,7 +405,8 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
             const Launch &L = launches[l];
             hipStream_t s = fork.stream((int)l);
             if (L.store == kStoreGlobal) PYHEA_HIP(launch_pad_fill(ddev + L.first, L.count, s));
-            PYHEA_HIP(launch_mc(ddev + L.first, L.count, L.store, L.M, L.S, L.B, L.H, L.lds, INT_MAX, s));
+            PYHEA_HIP(
+                launch_mc(ddev + L.first, L.count, L.store, L.M, L.S, L.B, L.W, L.bal, L.K, L.lds, INT_MAX, s));
             if (L.store == kStoreGlobal) PYHEA_HIP(launch_pad_drain(ddev + L.first, L.count, s));
         }
         PYHEA_HIP(fork.end());

@@ -96,7 +96,7 @@ struct Job {
     ChainDesc desc{};
     int store = kStoreLds8;
     int lds = 0;
-    int H = 1;
+    int W = 1, bal = 0, K = 1;
     JobLayout lay{};
 };
 
@@ -154,6 +154,7 @@ void fill_desc(Job *j) {
     d.state = (ChainState *)(base + j->lay.state);
     d.store = j->store;
     d.lds_bytes = j->lds;
+    d.sym = symmetric_target(j->target.data(), g.S, g.M);
 }
 
 CountTask count_task(const Job *j, bool recount) {
@@ -349,9 +350,9 @@ void Server::run() {
             continue;
         }
         // one round: group by launch shape, one stream per group
-        std::map<std::tuple<int, int, int, int, int>, std::vector<Job *>> groups;
+        std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<Job *>> groups;
         for (Job *j : run_set)
-            groups[{j->store, j->g.M, j->g.S, j->params.cand_per_step, j->H}].push_back(j);
+            groups[{j->store, j->g.M, j->g.S, j->params.cand_per_step, j->W, j->bal, j->K}].push_back(j);
         std::vector<ChainDesc> descs;
         std::vector<Job *> order;
         std::vector<std::pair<size_t, std::vector<Job *>>> launches;
@@ -375,7 +376,8 @@ void Server::run() {
             hipStream_t s = streams[1 + gi % (streams.size() - 1)];
             ok = hipStreamWaitEvent(s, ready, 0) == hipSuccess;
             ok = ok && launch_mc((const ChainDesc *)desc_dev + L.first, (int)L.second.size(), j0->store, j0->g.M,
-                                 j0->g.S, j0->params.cand_per_step, j0->H, lds, steps_per_round, s) == hipSuccess;
+                                 j0->g.S, j0->params.cand_per_step, j0->W, j0->bal, j0->K, lds, steps_per_round,
+                                 s) == hipSuccess;
         }
         for (size_t i = 1; i < streams.size(); ++i) ok = ok && hipStreamSynchronize(streams[i]) == hipSuccess;
         if (ready) (void)hipEventDestroy(ready);
@@ -522,10 +524,12 @@ pyhea_status pyhea_serve_submit(void *server, uint64_t job_id, const pyhea_latti
     const int E = g.S * g.M * g.M;
     j->target.assign(obj->target, obj->target + E);
     j->weight.assign(obj->weight, obj->weight + g.S);
-    const LaunchShape ls = choose_launch(g, params->cand_per_step, s->lds_budget, 0);
+    const LaunchShape ls = choose_launch(g, params->cand_per_step, s->lds_budget, 0, s->max_slots);
     j->store = ls.store;
     j->lds = ls.lds;
-    j->H = ls.H;
+    j->W = ls.W;
+    j->bal = ls.bal;
+    j->K = ls.K;
     j->footprint = job_footprint(g, j->store);
     std::lock_guard<std::mutex> lk(s->mu);
     if (j->footprint > s->budget) {

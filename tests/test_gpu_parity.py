@@ -216,7 +216,7 @@ def test_mc_zero_and_partial_budgets():
         assert_same_chain(o, g)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_store_variants_are_bit_identical(variant):
     lattice, L, M, S = orc.FCC, (6, 6, 6), 5, 3
     rng = np.random.default_rng(5)
@@ -226,6 +226,54 @@ def test_store_variants_are_bit_identical(variant):
         o, g = run_both(lattice, L, M, S, sp, tgt, w, seed=77, chain=3, T=8000, B=64)
     finally:
         pb.pyhea_tune_force(-1)
+    assert_same_chain(o, g)
+
+
+LOOKAHEAD_CASES = [
+    # lattice, L, M, S, B, mode, T, depth, target zero (few commits)
+    (orc.FCC, (6, 6, 6), 5, 3, 64, 0, 20_000, 0, True),   # long runs of steps without commits
+    (orc.FCC, (4, 4, 4), 4, 2, 64, 0, 10_000, 0, False),
+    (orc.BCC, (5, 4, 4), 3, 2, 48, 1, 6_000, 0, False),   # BEST, B < 64
+    (orc.FCC, (5, 4, 3), 5, 3, 100, 0, 5_001, 0, False),  # two slot groups per step, ragged tail
+    (orc.FCC, (4, 4, 4), 3, 2, 32, 0, 10**6, 9, True),    # depth limit inside a pass
+]
+
+
+@pytest.mark.parametrize("K,variant", [(1, 0), (2, 0), (3, 0), (5, 0), (8, 0), (2, 4), (5, 4)])
+@pytest.mark.parametrize("case", LOOKAHEAD_CASES)
+def test_lookahead_is_bit_identical(case, K, variant):
+    lattice, L, M, S, B, mode, T, depth, zero = case
+    rng = np.random.default_rng(sum(L) * 7 + M + B)
+    sp, tgt, w = random_problem(rng, lattice, L, M, S)
+    if zero:
+        tgt = np.zeros_like(tgt)
+    pb.pyhea_tune_force_lookahead(K)
+    pb.pyhea_tune_force(variant)
+    try:
+        o, g = run_both(lattice, L, M, S, sp, tgt, w, seed=4242, chain=K, T=T, B=B, mode=mode, depth=depth)
+    finally:
+        pb.pyhea_tune_force_lookahead(0)
+        pb.pyhea_tune_force(-1)
+    assert o[2]["steps"] > 0
+    assert_same_chain(o, g)
+
+
+@pytest.mark.parametrize("variant", [0, 4])
+@pytest.mark.parametrize("shape", [(orc.FCC, (4, 4, 4), 5, 2, 64), (orc.BCC, (5, 4, 4), 4, 3, 48),
+                                   (orc.FCC, (5, 4, 3), 6, 1, 100)])
+def test_asymmetric_target_matches_oracle(shape, variant):
+    # a target that differs from its transpose takes the kernel's general row path
+    lattice, L, M, S, B = shape
+    rng = np.random.default_rng(M * 13 + S)
+    sp, tgt, w = random_problem(rng, lattice, L, M, S)
+    tgt = tgt + rng.uniform(-0.05, 0.05, size=tgt.shape)
+    assert not np.array_equal(tgt, np.swapaxes(tgt, 1, 2))
+    pb.pyhea_tune_force(variant)
+    try:
+        o, g = run_both(lattice, L, M, S, sp, tgt, w, seed=99, chain=5, T=6000, B=B)
+    finally:
+        pb.pyhea_tune_force(-1)
+    assert o[2]["commits"] > 0
     assert_same_chain(o, g)
 
 
