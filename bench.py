@@ -34,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes per clock x clock
 METRIC = "MC trial swaps/sec + full-SRO eval GB/s; batched vs plain at equal SRO error"
 
 
@@ -80,6 +81,22 @@ def cpu_baseline(p, budget_s: float = 12.0):
                       f"{n_eval} full evaluations of one 32,000-site configuration",
             "full_eval_sites_per_s": n_eval * p.N / de,
             "full_eval_GBps": n_eval * p.N / de / 1e9}
+
+
+def recorded(profile: str, source: str, key: str):
+    """A figure recorded in a committed rocprofv3 summary, if that summary was
+    taken on the current kernel source (otherwise None)."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, "profiles", profile)).read()
+        sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2411_18906_amd", "csrc", source), "rb")
+                             .read()).hexdigest()[:16]
+    except OSError:
+        return None
+    vals = dict(l.split(":", 1) for l in text.splitlines() if ":" in l and not l.startswith((" ", "|", "#")))
+    if vals.get("kernel_source_sha256_prefix", "").strip() != sha or key not in vals:
+        return None
+    return float(vals[key])
 
 
 def recorded_traffic():
@@ -256,6 +273,16 @@ def main():
         out["chain"] = {"ms": float(ms.mean()), "trials": st["trials"], "commits": st["commits"],
                         "final_F": st["F"], "effective_trials_per_s":
                             (st["trials"] - st["null_trials"]) / (ms.mean() / 1e3)}
+    if "chain" in legs:
+        # the chain's own roofline: bytes gathered per trial 2(1 + Z) (Z = 42), and
+        # VALU lane operations per trial from the recorded instruction counts
+        tps = out["value"]
+        lane_ops = recorded("mc_chain_fcc20_counters.md", "mc_kernels.hip", "valu_lane_ops_per_trial")
+        out["roofline_chain"] = {
+            "bound": "latency", "gathered_bytes_per_trial": 86, "hbm_frac": tps * 86 / (HBM_PEAK_GBPS * 1e9),
+            "valu_lane_ops_per_trial": lane_ops,
+            "valu_frac_chip": None if lane_ops is None else tps * lane_ops / VALU_LANE_OPS_PEAK,
+            "valu_frac_one_cu": None if lane_ops is None else tps * lane_ops / (VALU_LANE_OPS_PEAK / 256)}
     if "eval" in legs:
         ms = np.array(leg_ms("eval0", "eval1"))
         alg_bytes = K * (N + S * M * M * 4 + 16)
@@ -267,6 +294,12 @@ def main():
                            "frac": gbps / HBM_PEAK_GBPS,
                            "traffic": None if tb is None else tb / (ms.mean() / 1e3) / 1e9,
                            "kernel": "full SRO evaluation (pair counts + objective) of the batch"}
+        # the same kernel against the VALU issue rate, from its recorded instruction count
+        ops = recorded("full_eval_fcc20_5sp_traffic.md", "sro_bits.hip", "valu_lane_ops_per_site")
+        if ops is not None:
+            cap = VALU_LANE_OPS_PEAK / ops / 1e9   # GB/s at one byte per site
+            out["roofline_valu"] = {"bound": "alu", "lane_ops_per_site": ops, "valu_cap_GBps": cap,
+                                    "frac": gbps / cap}
     if "eval3" in legs:
         ms = np.array(leg_ms("eval30", "eval31"))
         gbps = K3 * (p3.N + p3.S * p3.M * p3.M * 4 + 16) / (ms.mean() / 1e3) / 1e9

@@ -7,6 +7,10 @@
 
 namespace pyhea {
 
+// Members of the conflict-free set evaluated together by the speculative commit
+// phase (E = S M M entries per member).
+__host__ __device__ inline int spec_chunk(int E) { return E <= 128 ? 16 : 8; }
+
 // LDS layout of the MC kernel (must match the carve order in mc_kernels.hip).
 // W = wavefronts per slot group (>= S), bal = offsets spread evenly over them
 // (partial histograms exchanged through LDS), K = steps whose candidates one
@@ -18,11 +22,13 @@ __host__ __device__ inline int mc_lds_bytes(int S, int M, int B, int W = 0, int 
     int n = 0;
     n += r(E * 32);                               // entry records
     n += r(kMaxOffsets * 16) + r(kMaxOffsets * 4);     // dlin4, offmod
-    n += r(Bt * 8) + 5 * r(Bt * 4);               // rec_dS, p, q, pp, pq, ab
-    n += 3 * r(S * Bt * 8);                       // rec_cp, rec_cq, rec_dQ
+    n += r(Bt * 8) + 3 * r(Bt * 4);               // rec_dS, pp, pq, ab
+    n += 2 * r(S * Bt * (M > 6 ? 8 : 4));         // rec_cp, rec_cq (histograms)
+    n += r(S * Bt * 8);                           // rec_dQ
     n += 2 * r(Bt * 4);                           // order, list (per step of a pass)
     n += r(2 * kMaxShells * 8) + r(32 * 4);       // sh_dQ (two buffers), sh_int
     if (bal) n += r(S * W * 2 * Bt * (M > 6 ? 8 : 4));  // partial histograms
+    n += r(64 * 8) + r(spec_chunk(E) * E * 8) + r(16 * kMaxShells * 8);  // speculative commits
     return n;
 }
 

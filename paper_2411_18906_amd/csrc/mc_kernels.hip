@@ -68,19 +68,20 @@ struct Lds {
     int4 *dlin4;    // [kMaxOffsets]: linear deltas of offset t from bases 0..3
     int32_t *offmod;
     double *rec_dS;     // [B]
-    uint32_t *rec_p;    // [B]
-    uint32_t *rec_q;    // [B]
     uint32_t *rec_pp;   // [B] packed position of p (10 bits per axis)
     uint32_t *rec_pq;   // [B]
     uint32_t *rec_ab;   // [B] a | b << 8 | null << 16
-    uint64_t *rec_cp;   // [S][B]
-    uint64_t *rec_cq;   // [S][B]
+    void *rec_cp;       // [S][K B] neighbour histograms of p (Hist)
+    void *rec_cq;       // [S][K B] neighbour histograms of q (Hist)
     double *rec_dQ;     // [S][B]
     int32_t *order;     // [B]
     int32_t *list;      // [B]
     double *sh_dQ;      // [2][kMaxShells]
     int32_t *sh_int;    // scalars
     void *part;         // [S][W][2 (cp, cq)][K B] partial histograms (bal)
+    uint64_t *spec_cm;  // [64] earlier candidates each improving candidate conflicts with
+    double *spec_T;     // [CH][E] change of every entry's term under each member of a chunk
+    double *spec_Q;     // [16][kMaxShells] dQ_k of each member of a chunk
     uint8_t *store;     // species store
 };
 
@@ -128,6 +129,23 @@ __device__ __forceinline__ int wrap_axis(int v, int L) {
 
 __device__ __forceinline__ uint32_t pack_pos(int x, int y, int z) {
     return (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
+}
+
+// cell and basis of a packed position, and the site id p = ((cz Ly + cy) Lx + cx) A + b
+__device__ __forceinline__ SiteCoord pos_site(const ChainDesc &d, uint32_t pos) {
+    const int x = (int)(pos & 1023u), y = (int)((pos >> 10) & 1023u), z = (int)((pos >> 20) & 1023u);
+    const int bx = x & 1, by = y & 1, bz = z & 1;
+    SiteCoord c;
+    c.cx = x >> 1;
+    c.cy = y >> 1;
+    c.cz = z >> 1;
+    // FCC basis (0,0,0), (1,1,0), (1,0,1), (0,1,1); BCC (0,0,0), (1,1,1)
+    c.b = d.A == 2 ? bx : ((bx & by) ? 1 : ((bx & bz) ? 2 : ((by & bz) ? 3 : 0)));
+    return c;
+}
+
+__device__ __forceinline__ uint32_t site_id(const ChainDesc &d, SiteCoord c) {
+    return (uint32_t)(((c.cz * d.Ly + c.cy) * d.Lx + c.cx) * d.A + c.b);
 }
 
 // squared minimum-image distance (half units) between two packed positions
@@ -179,6 +197,22 @@ __device__ void write_site(const Lds &L, const ChainDesc &d, int cx, int cy, int
             for (int px = x0; px < d.PX; px += d.Lx) store_species<kStore>(L, d, padded_id(d, px, py, pz, b), v);
 }
 
+// change of entry (i, j) of shell k's counts when candidate s (record index) commits
+template <int M, typename Hist>
+__device__ __forceinline__ int entry_dn(const Lds &L, int Bt, int r, int k, int i, int j) {
+    const uint32_t ab = L.rec_ab[r];
+    const int a = (int)(ab & 0xFFu), b = (int)((ab >> 8) & 0xFFu);
+    const Hist cp = ((const Hist *)L.rec_cp)[k * Bt + r], cq = ((const Hist *)L.rec_cq)[k * Bt + r];
+    const int ui = (i == a ? 1 : 0) - (i == b ? 1 : 0), uj = (j == a ? 1 : 0) - (j == b ? 1 : 0);
+    return __mul24(ui, fld(cq, j) - fld(cp, j)) + __mul24(uj, fld(cq, i) - fld(cp, i));
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ int sel4(int4 v, int b) {
     return b == 0 ? v.x : (b == 1 ? v.y : (b == 2 ? v.z : v.w));
 }
@@ -216,19 +250,20 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
         L.dlin4 = (int4 *)carve(p, kMaxOffsets * 16);
         L.offmod = (int32_t *)carve(p, kMaxOffsets * 4);
         L.rec_dS = (double *)carve(p, Bt * 8);
-        L.rec_p = (uint32_t *)carve(p, Bt * 4);
-        L.rec_q = (uint32_t *)carve(p, Bt * 4);
         L.rec_pp = (uint32_t *)carve(p, Bt * 4);
         L.rec_pq = (uint32_t *)carve(p, Bt * 4);
         L.rec_ab = (uint32_t *)carve(p, Bt * 4);
-        L.rec_cp = (uint64_t *)carve(p, S * Bt * 8);
-        L.rec_cq = (uint64_t *)carve(p, S * Bt * 8);
+        L.rec_cp = carve(p, S * Bt * (int)sizeof(Hist));
+        L.rec_cq = carve(p, S * Bt * (int)sizeof(Hist));
         L.rec_dQ = (double *)carve(p, S * Bt * 8);
         L.order = (int32_t *)carve(p, Bt * 4);
         L.list = (int32_t *)carve(p, Bt * 4);
         L.sh_dQ = (double *)carve(p, 2 * kMaxShells * 8);
         L.sh_int = (int32_t *)carve(p, 32 * 4);
         if (bal) L.part = carve(p, S * W * 2 * Bt * (int)sizeof(Hist));
+        L.spec_cm = (uint64_t *)carve(p, kWave * 8);
+        L.spec_T = (double *)carve(p, spec_chunk(E) * E * 8);
+        L.spec_Q = (double *)carve(p, 16 * kMaxShells * 8);
         L.store = p;
     }
 
@@ -460,12 +495,10 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                 }
             }
             if (k >= 0 && slot < B && kw < ke) {
-                L.rec_cp[k * Bt + rix] = (uint64_t)cp;
-                L.rec_cq[k * Bt + rix] = (uint64_t)cq;
+                ((Hist *)L.rec_cp)[k * Bt + rix] = cp;
+                ((Hist *)L.rec_cq)[k * Bt + rix] = cq;
                 L.rec_dQ[k * Bt + rix] = dQ;
                 if (k == 0) {
-                    L.rec_p[rix] = p;
-                    L.rec_q[rix] = q;
                     L.rec_pp[rix] = ppos;
                     L.rec_pq[rix] = qpos;
                     L.rec_ab[rix] = (uint32_t)a | ((uint32_t)b << 8) |
@@ -581,12 +614,133 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
         // per re-validated candidate to add the shells' dQ.  Site writes wait
         // until the end of the phase: later candidates never read committed sites.
         int n_commit = 0;
+        const bool spec = d.mode == PYHEA_MODE_DISJOINT && n_impr >= 3 && n_impr <= kWave;
+        if (spec) {
+            // The same rule, evaluated speculatively.  cm[u] marks the earlier
+            // candidates that candidate u conflicts with.  The greedy conflict-free
+            // set I of the undecided candidates is evaluated against the running
+            // counts as if every member commits, CH members at a time; members
+            // before the first one that fails re-validation commit, exactly as they
+            // would one by one, and the search resumes after the failed member.
+            const int CH = spec_chunk(E);
+            const int nwaves = nthreads / kWave;
+            for (int u = wave; u < n_impr; u += nwaves) {
+                const int su = L.order[rb + u];
+                const uint32_t up = L.rec_pp[rb + su], uq = L.rec_pq[rb + su];
+                bool hit = false;
+                if (lane < u) {
+                    const int sv = L.order[rb + lane];
+                    const uint32_t vp = L.rec_pp[rb + sv], vq = L.rec_pq[rb + sv];
+                    hit = near_or_equal(d, up, vp) || near_or_equal(d, up, vq) || near_or_equal(d, uq, vp) ||
+                          near_or_equal(d, uq, vq);
+                }
+                const uint64_t mk = ballot64(hit);
+                if (lane == 0) L.spec_cm[u] = mk;
+            }
+            __syncthreads();
+            const uint64_t my_cm = lane < n_impr ? L.spec_cm[lane] : 0ull;
+            const bool own = (int)threadIdx.x < E;   // this thread's entry of the counts
+            const int e = threadIdx.x;
+            const int ek = own ? e / (M * M) : 0, ei = own ? (e / M) % M : 0, ej = own ? e % M : 0;
+            uint64_t committed = 0;
+            int next = 0;
+            while (next < n_impr) {
+                uint64_t I = 0;
+                for (int u = next; u < n_impr; ++u)
+                    if ((readlane_u64(my_cm, u) & (committed | I)) == 0) I |= 1ull << u;
+                int fail_u = -1;
+                while (I) {
+                    uint64_t chunk = 0;
+                    int m = 0;
+                    for (uint64_t t2 = I; t2 && m < CH; t2 &= t2 - 1, ++m) chunk |= t2 & (~t2 + 1ull);
+                    // every entry's term change under each member, in rank order
+                    int cnt0 = 0, run = 0;
+                    double Rv = 0.0, tv = 0.0;
+                    if (own) {
+                        const Ent en = L.ent[e];
+                        cnt0 = run = en.cnt;
+                        Rv = en.R;
+                        tv = en.t;
+                        int vi = 0;
+                        for (uint64_t t2 = chunk; t2; t2 &= t2 - 1, ++vi) {
+                            const int r = rb + L.order[rb + __ffsll((long long)t2) - 1];
+                            const int dn = entry_dn<M, Hist>(L, Bt, r, ek, ei, ej);
+                            double delta = 0.0;
+                            if (dn != 0) {
+                                delta = sq_dev(run + dn, Rv, tv) - sq_dev(run, Rv, tv);
+                                run += dn;
+                            }
+                            L.spec_T[vi * E + e] = delta;
+                        }
+                    }
+                    __syncthreads();
+                    // dQ_k per member: rows in order, each row's terms in order (terms
+                    // of unchanged entries are exactly +0.0)
+                    for (int it = threadIdx.x; it < m * S; it += nthreads) {
+                        const int vi = it / S, kk = it - vi * S;
+                        const double *T = L.spec_T + vi * E + kk * M * M;
+                        double Q = 0.0;
+#pragma unroll
+                        for (int i = 0; i < M; ++i) {
+                            double rs = 0.0;
+#pragma unroll
+                            for (int j = 0; j < M; ++j) rs = rs + T[i * M + j];
+                            Q = Q + rs;
+                        }
+                        L.spec_Q[vi * kMaxShells + kk] = Q;
+                    }
+                    __syncthreads();
+                    // the first member whose dS fails (the step's first commit is not
+                    // re-validated); every wavefront finds the same one
+                    bool fails = false;
+                    if (lane < m) {
+                        double dS = 0.0;
+#pragma unroll
+                        for (int kk = 0; kk < kMaxShells; ++kk)
+                            if (kk < S) dS = dS + wk[kk] * L.spec_Q[lane * kMaxShells + kk];
+                        fails = !(dS < -tau) && !(n_commit == 0 && lane == 0);
+                    }
+                    const uint64_t fm = ballot64(fails);
+                    const int f = fm ? __ffsll((long long)fm) - 1 : m;
+                    if (own) {
+                        int r2 = run;
+                        if (f < m) {
+                            r2 = cnt0;
+                            int vi = 0;
+                            for (uint64_t t2 = chunk; t2 && vi < f; t2 &= t2 - 1, ++vi)
+                                r2 += entry_dn<M, Hist>(L, Bt, rb + L.order[rb + __ffsll((long long)t2) - 1], ek, ei, ej);
+                        }
+                        if (r2 != cnt0) {
+                            Ent en = L.ent[e];
+                            en.cnt = r2;
+                            en.sq = sq_dev(r2, Rv, tv);
+                            L.ent[e] = en;
+                        }
+                    }
+                    {
+                        int vi = 0;
+                        uint64_t t2 = chunk;
+                        for (; vi < f; t2 &= t2 - 1, ++vi) {
+                            const int u = __ffsll((long long)t2) - 1;
+                            if (threadIdx.x == 0) L.list[n_commit + vi] = L.order[rb + u];
+                            committed |= 1ull << u;
+                        }
+                        if (f < m) fail_u = __ffsll((long long)t2) - 1;
+                    }
+                    n_commit += f;
+                    I &= ~chunk;
+                    __syncthreads();
+                    if (f < m) break;
+                }
+                next = fail_u >= 0 ? fail_u + 1 : n_impr;
+            }
+        }
         int n_meet = 0;
         uint32_t cpr[kMaxB / 32];
 #pragma unroll
         for (int r = 0; r < kMaxB / 32; ++r) cpr[r] = 0;
         const bool ewave = grp == 0 && k >= 0;   // one wave per shell handles its entries
-        for (int u = 0; u < n_impr; ++u) {
+        for (int u = 0; !spec && u < n_impr; ++u) {
             if (d.mode == PYHEA_MODE_BEST && n_commit > 0) break;
             const int s = L.order[rb + u];
             const uint32_t upp = L.rec_pp[rb + s], upq = L.rec_pq[rb + s];
@@ -604,7 +758,8 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
             int dn = 0;
             int e = 0;
             if (ewave && lane < M * M) {
-                const Hist cp = (Hist)L.rec_cp[k * Bt + rb + s], cq = (Hist)L.rec_cq[k * Bt + rb + s];
+                const Hist cp = ((const Hist *)L.rec_cp)[k * Bt + rb + s];
+                const Hist cq = ((const Hist *)L.rec_cq)[k * Bt + rb + s];
                 const int i = lane / M, j = lane - (lane / M) * M;
                 const int ui = (i == a ? 1 : 0) - (i == b ? 1 : 0), uj = (j == a ? 1 : 0) - (j == b ? 1 : 0);
                 dn = __mul24(ui, fld(cq, j) - fld(cp, j)) + __mul24(uj, fld(cq, i) - fld(cp, i));
@@ -667,9 +822,8 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
             const int s = L.list[t >> 1];
             const int side = t & 1;
             const uint32_t ab = L.rec_ab[rb + s];
-            const uint32_t site = side ? L.rec_q[rb + s] : L.rec_p[rb + s];
+            const SiteCoord sc = pos_site(d, side ? L.rec_pq[rb + s] : L.rec_pp[rb + s]);
             const int v = side ? (int)(ab & 0xFFu) : (int)((ab >> 8) & 0xFFu);
-            const SiteCoord sc = site_coord(site, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
             write_site<kStore>(L, d, sc.cx, sc.cy, sc.cz, sc.b, v);
         }
         if (d.log) {
@@ -680,8 +834,8 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                     uint32_t *rec = d.log + 4 * at;
                     rec[0] = (uint32_t)step;
                     rec[1] = (uint32_t)s;
-                    rec[2] = L.rec_p[rb + s];
-                    rec[3] = L.rec_q[rb + s];
+                    rec[2] = site_id(d, pos_site(d, L.rec_pp[rb + s]));
+                    rec[3] = site_id(d, pos_site(d, L.rec_pq[rb + s]));
                 }
             }
         }

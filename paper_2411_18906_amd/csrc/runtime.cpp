@@ -167,8 +167,10 @@ struct DeviceBuffer {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Auxiliary streams (default priority, non-blocking) on which launches of
-// different shapes run side by side; created once per device, kept until exit.
-constexpr int kAuxStreams = 4;
+// different shapes run beside the caller's stream; created once per device,
+// kept until exit.  Three, so that with the caller's stream they map onto the
+// four hardware queues a process gets by default.
+constexpr int kAuxStreams = 3;
 
 bool aux_streams(hipStream_t *out) {
     static std::mutex mu;
@@ -195,10 +197,11 @@ struct Fork {
     ~Fork() {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
     }
-    hipError_t begin(hipStream_t m, int n_streams) {
+    // launch i goes to the caller's stream (i % (used + 1) == 0) or aux stream
+    hipError_t begin(hipStream_t m, int n_launches) {
         main = m;
-        used = std::min(n_streams, kAuxStreams);
-        if (used <= 1 || !aux_streams(aux)) {
+        used = std::min(n_launches - 1, kAuxStreams);
+        if (used <= 0 || !aux_streams(aux)) {
             used = 0;  // everything stays on the caller's stream
             return hipSuccess;
         }
@@ -211,7 +214,10 @@ struct Fork {
             if ((r = hipStreamWaitEvent(aux[i], e, 0)) != hipSuccess) return r;
         return hipSuccess;
     }
-    hipStream_t stream(int i) const { return used ? aux[i % used] : main; }
+    hipStream_t stream(int i) const {
+        const int r = used ? i % (used + 1) : 0;
+        return r == 0 ? main : aux[r - 1];
+    }
     hipError_t end() {
         for (int i = 0; i < used; ++i) {
             hipEvent_t e;

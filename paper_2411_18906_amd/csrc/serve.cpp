@@ -373,13 +373,13 @@ void Server::run() {
             const Job *j0 = L.second[0];
             int lds = 0;
             for (Job *j : L.second) lds = std::max(lds, j->lds);
-            hipStream_t s = streams[1 + gi % (streams.size() - 1)];
-            ok = hipStreamWaitEvent(s, ready, 0) == hipSuccess;
+            hipStream_t s = streams[gi % streams.size()];
+            ok = s == s0 || hipStreamWaitEvent(s, ready, 0) == hipSuccess;
             ok = ok && launch_mc((const ChainDesc *)desc_dev + L.first, (int)L.second.size(), j0->store, j0->g.M,
                                  j0->g.S, j0->params.cand_per_step, j0->W, j0->bal, j0->K, lds, steps_per_round,
                                  s) == hipSuccess;
         }
-        for (size_t i = 1; i < streams.size(); ++i) ok = ok && hipStreamSynchronize(streams[i]) == hipSuccess;
+        for (size_t i = 0; i < streams.size(); ++i) ok = ok && hipStreamSynchronize(streams[i]) == hipSuccess;
         if (ready) (void)hipEventDestroy(ready);
         // every job's state in one read-back
         states.resize(order.size());
@@ -451,7 +451,7 @@ pyhea_status pyhea_serve_open(int64_t hbm_budget_bytes, int32_t max_slots, int32
     s->max_slots = max_slots;
     s->steps_per_round = steps_per_round > 0 ? steps_per_round : 256;
     s->lds_budget = max_lds_per_block();
-    s->streams.resize(4);  // [0]: admission, retirement and read-back; [1..3]: the rounds' launches
+    s->streams.resize(4);  // [0]: admission, retirement and read-back; all four: the rounds' launches
     for (auto &st : s->streams) {
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
             delete s;
