@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpyhea.so")
 OK, EINVAL, ENOMEM, EDEVICE, EBUSY, ECANCELLED, ENOSYS, ENOENT = 0, -1, -2, -3, -4, -5, -6, -7
 FCC, BCC = 0, 1
 MODE_DISJOINT, MODE_BEST = 0, 1
+STOP_TRIALS, STOP_DEPTH = 0, 1
 
 EXPORTS = [
     "pyhea_version", "pyhea_last_error", "pyhea_sro_eval", "pyhea_sro_eval_batch",

@@ -201,7 +201,7 @@ def test_mc_depth_limit_and_tau():
     rng = np.random.default_rng(3)
     sp, tgt, w = random_problem(rng, lattice, L, M, S)
     o, g = run_both(lattice, L, M, S, sp, tgt, w, seed=1, chain=0, T=10**6, B=32, depth=6)
-    assert o[2]["stop_reason"] == pb.MODE_BEST  # == 1: depth reached
+    assert o[2]["stop_reason"] == pb.STOP_DEPTH
     assert_same_chain(o, g)
     o, g = run_both(lattice, L, M, S, sp, tgt, w, seed=2, chain=0, T=4000, B=16, mode=1, tau=1e-3)
     assert_same_chain(o, g)
