@@ -124,12 +124,11 @@ pyhea_status pyhea_sro_eval_batch(const pyhea_lattice *lat, int64_t n_configs, c
     double *tdev = (double *)((char *)buf.ptr + tw_off);
     EvalDesc ed;
     fill_eval_desc(g, &ed);
-    std::vector<double> tw(E + kMaxShells, 0.0);
     if (obj) {
-        std::memcpy(tw.data(), obj->target, E * 8);
-        std::memcpy(tw.data() + E, obj->weight, g.S * 8);
-        // from pageable memory the runtime performs this copy synchronously, so tw may go out of scope
-        PYHEA_HIP(hipMemcpyAsync(tdev, tw.data(), tw.size() * 8, hipMemcpyHostToDevice, stream));
+        SmallTable tw{};
+        std::memcpy(tw.v, obj->target, E * 8);
+        std::memcpy(tw.v + E, obj->weight, g.S * 8);
+        PYHEA_HIP(launch_upload(tw, E + kMaxShells, tdev, stream));
     }
     bool fused = false;
     {

@@ -85,6 +85,14 @@ hipError_t launch_count_tasks(const CountTask *tasks, const uint32_t *tile0, int
 
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t stream);
 
+// Target and weight tables (at most S M M + S doubles) copied to the device by a
+// kernel whose arguments carry them: stream-ordered, and the host never waits.
+constexpr int kMaxTable = kMaxShells * kMaxSpecies * kMaxSpecies + kMaxShells;
+struct SmallTable {
+    double v[kMaxTable];
+};
+hipError_t launch_upload(const SmallTable &t, int n, double *dst, hipStream_t stream);
+
 hipError_t launch_count_gather(const EvalDesc &ed, int64_t K, const int8_t *species,
                                int32_t *counts, int32_t *bad, hipStream_t stream);
 hipError_t launch_objective_epilogue(const EvalDesc &ed, int64_t K, const int32_t *counts,

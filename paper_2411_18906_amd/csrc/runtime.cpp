@@ -141,7 +141,7 @@ pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, 
     if (forced != 0 && fill_bit_desc(g, max_lds_per_block(), K, &bd)) {
         void *partial = nullptr;
         if (bd.nchunks > 1) PYHEA_HIP(hipMallocAsync(&partial, (size_t)K * bd.partial_stride * 4, stream));
-        const bool fuse = S_F && bd.nchunks == 1;
+        const bool fuse = S_F != nullptr;   // the counting launch finishes Eq. 2-3 too
         const hipError_t e = launch_count_bits(g, bd, K, species, (int32_t *)partial, counts, bad,
                                                fuse ? tw : nullptr, fuse ? S_F : nullptr, stream);
         if (partial) (void)hipFreeAsync(partial, stream);

@@ -64,8 +64,94 @@ __device__ __forceinline__ int wave_sum(int v) {
 // floor(n / d) for small non-negative n, d (see div_small)
 __device__ __forceinline__ int qdiv(int n, double inv) { return (int)div_small((uint32_t)n, inv); }
 
+// Counts of one configuration from its pair sums (S x NP, then n_0..n_{M-2}, then the
+// bad-species flag), rows completed from the row-sum identity sum_j N_ij = z_k n_i,
+// then Eq. 2-3: R = N / (n_i n_j z_k), alpha = 1 - N_ij R, each row's (alpha - t)^2
+// summed over j, Q_k the sum of the rows, S = sum_k w_k Q_k, F = sqrt(S).  All
+// threads of the block call it; lc, lsq, lrow are LDS scratch.
 template <int M, int S>
-__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4)))
+__device__ __forceinline__ void epilogue(const int32_t *pairs, const BitDesc &bd, int32_t *lc, double *lsq, double *lrow,
+                         int32_t *cnt, int32_t *bad_out, const double *tw, double *S_F) {
+    constexpr int P = Pairs<M>::P;
+    constexpr int NP = Pairs<M>::NP;
+    int64_t n[M];
+    {
+        int64_t rest = bd.N;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            n[i] = pairs[S * NP + i];
+            rest -= n[i];
+        }
+        n[M - 1] = rest;
+    }
+    const bool bad = pairs[S * NP + P] != 0;
+    if (threadIdx.x < S) {
+        const int k = threadIdx.x;
+        const int32_t *pa = pairs + k * NP;
+        int32_t *c = lc + k * M * M;
+        int q = 0;
+        for (int i = 0; i < P; ++i) {
+            c[i * M + i] = 2 * pa[q++];
+            for (int j = i + 1; j < P; ++j) {
+                c[i * M + j] = pa[q];
+                c[j * M + i] = pa[q];
+                ++q;
+            }
+        }
+        int64_t last = 0;
+        for (int i = 0; i < P; ++i) {
+            int64_t r = (int64_t)bd.zk[k] * n[i];
+            for (int j = 0; j < P; ++j) r -= c[i * M + j];
+            c[i * M + (M - 1)] = (int32_t)r;
+            c[(M - 1) * M + i] = (int32_t)r;
+            last += r;
+        }
+        c[(M - 1) * M + (M - 1)] = (int32_t)((int64_t)bd.zk[k] * n[M - 1] - last);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < S * M * M; e += blockDim.x) {
+        cnt[e] = lc[e];
+        if (S_F) {
+            const int k = e / (M * M), i = (e / M) % M, j = e % M;
+            const double R = (double)bd.N / (double)(n[i] * n[j] * (int64_t)bd.zk[k]);
+            const double a = 1.0 - (double)lc[e] * R;
+            const double dd = a - tw[e];
+            lsq[e] = dd * dd;
+        }
+    }
+    if (threadIdx.x == 0) *bad_out = bad ? 1 : 0;
+    if (S_F) {
+        __syncthreads();
+        for (int r = threadIdx.x; r < S * M; r += blockDim.x) {
+            double row = 0.0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) row = row + lsq[r * M + j];
+            lrow[r] = row;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            bool ok = !bad;
+#pragma unroll
+            for (int i = 0; i < M; ++i) ok = ok && n[i] > 0;
+            double sum = 0.0;
+            for (int k = 0; k < S; ++k) {
+                double Q = 0.0;
+#pragma unroll
+                for (int i = 0; i < M; ++i) Q = Q + lrow[k * M + i];
+                sum = sum + tw[S * M * M + k] * Q;
+            }
+            const double nan = __longlong_as_double(0x7ff8000000000000ll);
+            S_F[0] = ok ? sum : nan;
+            S_F[1] = ok ? sqrt(sum) : nan;
+        }
+    }
+}
+
+// MaxW: the wavefronts per SIMD the register allocation aims for -- 4 for a
+// workgroup alone on its CU (registers spent on overlapping loads), 8 when
+// several workgroups share the CU.
+template <int M, int S, int MaxW>
+__global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4, MaxW)))
 count_bits_kernel(BitDesc bd, int64_t K,
                                                                const int8_t *__restrict__ species,
                                                                int32_t *__restrict__ partial,
@@ -281,78 +367,13 @@ count_bits_kernel(BitDesc bd, int64_t K,
         return;
     }
     // ---- 4. one workgroup holds the whole configuration: counts and Eq. 2-3 here ----
-    int32_t *cnt = counts_out + kc * (int64_t)(S * M * M);
-    // epilogue scratch after the offset table: [S][M][M] counts, then [S][M][M] doubles
+    // epilogue scratch after the offset table: [S][M][M] counts, [S][M][M] and [S][M] doubles
     int32_t *lc = tab + 8 * bd.nh;
     double *lsq = reinterpret_cast<double *>((reinterpret_cast<uintptr_t>(lc + S * M * M) + 7) & ~uintptr_t(7));
-    int64_t n[M];
-    {
-        int64_t rest = bd.N;
-#pragma unroll
-        for (int i = 0; i < P; ++i) {
-            n[i] = red[S * NP + i];
-            rest -= n[i];
-        }
-        n[M - 1] = rest;
-    }
-    const bool bad = red[S * NP + P] != 0;
-    if (threadIdx.x < S) {
-        const int k = threadIdx.x;
-        const int32_t *pa = red + k * NP;
-        int32_t *c = lc + k * M * M;
-        int q = 0;
-        for (int i = 0; i < P; ++i) {
-            c[i * M + i] = 2 * pa[q++];
-            for (int j = i + 1; j < P; ++j) {
-                c[i * M + j] = pa[q];
-                c[j * M + i] = pa[q];
-                ++q;
-            }
-        }
-        int64_t last = 0;
-        for (int i = 0; i < P; ++i) {
-            int64_t r = (int64_t)bd.zk[k] * n[i];
-            for (int j = 0; j < P; ++j) r -= c[i * M + j];
-            c[i * M + (M - 1)] = (int32_t)r;
-            c[(M - 1) * M + i] = (int32_t)r;
-            last += r;
-        }
-        c[(M - 1) * M + (M - 1)] = (int32_t)((int64_t)bd.zk[k] * n[M - 1] - last);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < S * M * M; e += blockDim.x) {
-        cnt[e] = lc[e];
-        if (S_F) {
-            const int k = e / (M * M), i = (e / M) % M, j = e % M;
-            const double R = (double)bd.N / (double)(n[i] * n[j] * (int64_t)bd.zk[k]);
-            const double a = 1.0 - (double)lc[e] * R;
-            const double dd = a - tw[e];
-            lsq[e] = dd * dd;
-        }
-    }
-    if (threadIdx.x == 0) bad_out[kc] = bad ? 1 : 0;
-    if (S_F) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            bool ok = !bad;
-#pragma unroll
-            for (int i = 0; i < M; ++i) ok = ok && n[i] > 0;
-            double sum = 0.0;
-            for (int k = 0; k < S; ++k) {
-                double Q = 0.0;
-                for (int i = 0; i < M; ++i) {
-                    double row = 0.0;
-                    for (int j = 0; j < M; ++j) row = row + lsq[(k * M + i) * M + j];
-                    Q = Q + row;
-                }
-                sum = sum + tw[S * M * M + k] * Q;
-            }
-            const double nan = __longlong_as_double(0x7ff8000000000000ll);
-            S_F[2 * kc] = ok ? sum : nan;
-            S_F[2 * kc + 1] = ok ? sqrt(sum) : nan;
-        }
-    }
+    epilogue<M, S>(red, bd, lc, lsq, lsq + S * M * M, counts_out + kc * (int64_t)(S * M * M), bad_out + kc, tw,
+                   S_F ? S_F + 2 * kc : nullptr);
 }
+
 
 // partial sums -> full counts N[k][i][j] (one thread per configuration)
 template <int M, int S>
@@ -396,6 +417,21 @@ __global__ void finalize_bits_kernel(BitDesc bd, int64_t K, const int32_t *__res
     }
 }
 
+// partial sums -> counts and Eq. 2-3 (one 64-thread block per configuration)
+template <int M, int S>
+__global__ void __launch_bounds__(64) finalize_objective_kernel(BitDesc bd, const int32_t *__restrict__ partial,
+                                                               int32_t *__restrict__ counts,
+                                                               int32_t *__restrict__ bad,
+                                                               const double *__restrict__ tw,
+                                                               double *__restrict__ S_F) {
+    __shared__ int32_t lc[S * M * M];
+    __shared__ double lsq[S * M * M];
+    __shared__ double lrow[S * M];
+    const int64_t kc = blockIdx.x;
+    epilogue<M, S>(partial + kc * bd.partial_stride, bd, lc, lsq, lrow, counts + kc * (int64_t)(S * M * M), bad + kc,
+                   tw, S_F + 2 * kc);
+}
+
 __global__ void zero_kernel(int32_t *p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0;
@@ -406,8 +442,9 @@ hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_
                      int32_t *bad, const double *tw, double *S_F, hipStream_t stream) {
     const int P = M - 1;
     const size_t lds = ((size_t)(bd.ZC + 1) * 4 * P * bd.PW + bd.LW + S * Pairs<M>::NP + P + 1 + 8 * bd.nh + 1 +
-                        3 * S * M * M + 2) * 4;
-    const void *fn = (const void *)count_bits_kernel<M, S>;
+                        3 * S * M * M + 2 * S * M + 2) * 4;
+    const bool lone = bd.threads > 512;   // one workgroup per CU
+    const void *fn = lone ? (const void *)count_bits_kernel<M, S, 4> : (const void *)count_bits_kernel<M, S, 8>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (bd.nchunks > 1) {
@@ -417,11 +454,19 @@ hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_
     }
     for (int64_t k0 = 0; k0 < K; k0 += 65535) {
         const int64_t kn = std::min<int64_t>(65535, K - k0);
-        hipLaunchKernelGGL((count_bits_kernel<M, S>), dim3(bd.nchunks, (unsigned)kn), dim3(bd.threads), lds, stream,
-                           bd, kn, species + k0 * (int64_t)bd.N, partial + k0 * bd.partial_stride,
-                           counts + k0 * (int64_t)(S * M * M), bad + k0, tw, S_F ? S_F + 2 * k0 : nullptr);
+        if (!lone)
+            hipLaunchKernelGGL((count_bits_kernel<M, S, 8>), dim3(bd.nchunks, (unsigned)kn), dim3(bd.threads), lds, stream,
+                               bd, kn, species + k0 * (int64_t)bd.N, partial + k0 * bd.partial_stride,
+                               counts + k0 * (int64_t)(S * M * M), bad + k0, tw, S_F ? S_F + 2 * k0 : nullptr);
+        else
+            hipLaunchKernelGGL((count_bits_kernel<M, S, 4>), dim3(bd.nchunks, (unsigned)kn), dim3(bd.threads), lds, stream,
+                               bd, kn, species + k0 * (int64_t)bd.N, partial + k0 * bd.partial_stride,
+                               counts + k0 * (int64_t)(S * M * M), bad + k0, tw, S_F ? S_F + 2 * k0 : nullptr);
     }
-    if (bd.nchunks > 1)
+    if (bd.nchunks > 1 && S_F)
+        hipLaunchKernelGGL((finalize_objective_kernel<M, S>), dim3((unsigned)K), dim3(64), 0, stream, bd, partial,
+                           counts, bad, tw, S_F);
+    else if (bd.nchunks > 1)
         hipLaunchKernelGGL((finalize_bits_kernel<M, S>), dim3((unsigned)((K + 127) / 128)), dim3(128), 0, stream, bd, K,
                            partial, counts, bad);
     return hipGetLastError();
@@ -476,7 +521,7 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, BitDesc *bd) {
     bd->partial_stride = ((g.S * np + P + 1) + 3) & ~3;
     for (int k = 0; k < kMaxShells; ++k) bd->zk[k] = k < g.S ? g.z[k] : 0;
     // largest z-chunk whose planes fit in LDS
-    const int fixed = (bd->LW + g.S * np + P + 1 + 8 * kMaxOffsets / 2 + 3 * g.S * g.M * g.M + 3) * 4;
+    const int fixed = (bd->LW + g.S * np + P + 1 + 8 * kMaxOffsets / 2 + 3 * g.S * g.M * g.M + 2 * g.S * g.M + 3) * 4;
     const int per_layer = 4 * P * bd->PW * 4;
     int zc = (lds_budget - fixed) / per_layer - 1;
     if (zc < 1) return false;
@@ -487,7 +532,9 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, BitDesc *bd) {
     if (want > 1) zc = std::min<int64_t>(zc, std::max<int64_t>(2, (g.L[2] + want - 1) / want));
     bd->ZC = zc;
     bd->nchunks = (g.L[2] + zc - 1) / zc;
-    bd->threads = 512;
+    // a workgroup that needs more than half the LDS runs alone on its CU: give it
+    // 16 wavefronts so the CU still has latency to hide behind
+    bd->threads = fixed + (zc + 1) * per_layer > lds_budget / 2 ? 1024 : 512;
     // half offsets ordered by shell
     int nh = 0;
     for (int k = 0; k < g.S; ++k) {

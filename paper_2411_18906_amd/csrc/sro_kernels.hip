@@ -153,6 +153,10 @@ __global__ void __launch_bounds__(256) count_tasks_kernel(const CountTask *__res
     if (threadIdx.x == 0 && bad_sh) atomicOr(t.bad, 1);
 }
 
+__global__ void upload_kernel(SmallTable t, int n, double *__restrict__ dst) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = t.v[i];
+}
+
 __global__ void zero_i32_kernel(int32_t *p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0;
@@ -319,6 +323,13 @@ hipError_t launch_count_gather(const EvalDesc &ed, int64_t K, const int8_t *spec
     const int gy = (int)std::min<int64_t>(K, 65535);
     hipLaunchKernelGGL(count_gather_kernel, dim3(per_cfg, gy), dim3(256), 0, stream, ed, K, species,
                        counts, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_upload(const SmallTable &t, int n, double *dst, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    if (n > kMaxTable) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(upload_kernel, dim3(1), dim3(256), 0, stream, t, n, dst);
     return hipGetLastError();
 }
 
