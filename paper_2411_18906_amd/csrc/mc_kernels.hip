@@ -213,10 +213,6 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ int sel4(int4 v, int b) {
-    return b == 0 ? v.x : (b == 1 ? v.y : (b == 2 ? v.z : v.w));
-}
-
 template <int kStore, int M>
 __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ descs,
                                                   int32_t max_steps, int32_t W, int32_t bal, int32_t K) {
@@ -349,29 +345,51 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
             const int64_t left = d.n_trials - trials - (int64_t)kw * B;
             const int tasks_w = left <= 0 ? 0 : (left < B ? (int)left : B);
             const bool active = kw < ke && slot < tasks_w;
-            uint32_t p = 0, q = 0, ppos = 0, qpos = 0;
+            uint32_t ppos = 0, qpos = 0;
             int a = 0, b = 0;
             bool live = false;
             Hist cp = 0, cq = 0;   // the owner's full shell-k histograms
             double dQ = 0.0;
+            // the draws, the two sites and their species: once per candidate, by the
+            // group's first wavefront, shared with the others through the records
+            if (widx == 0 && slot < B && kw < ke) {
+                uint32_t ab = 0;
+                if (active) {
+                    uint32_t c[4] = {(uint32_t)slot, (uint32_t)(step + kw), d.chain_id, 0u};
+                    philox4x32_10(c, key0, key1);
+                    const uint32_t p = __umulhi(c[0], d.N), q = __umulhi(c[1], d.N);
+                    const SiteCoord sp = site_coord(p, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
+                    const SiteCoord sq = site_coord(q, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
+                    int bx, by, bz;
+                    basis_bits(d.A, sp.b, bx, by, bz);
+                    ppos = pack_pos(2 * sp.cx + bx, 2 * sp.cy + by, 2 * sp.cz + bz);
+                    basis_bits(d.A, sq.b, bx, by, bz);
+                    qpos = pack_pos(2 * sq.cx + bx, 2 * sq.cy + by, 2 * sq.cz + bz);
+                    a = load_species<kStore>(L, d, padded_id(d, sp.cx + h, sp.cy + h, sp.cz + h, sp.b));
+                    b = load_species<kStore>(L, d, padded_id(d, sq.cx + h, sq.cy + h, sq.cz + h, sq.b));
+                    ab = (uint32_t)a | ((uint32_t)b << 8) | ((uint32_t)(a == b) << 16) | (1u << 17);
+                }
+                L.rec_pp[rix] = ppos;
+                L.rec_pq[rix] = qpos;
+                L.rec_ab[rix] = ab;
+            }
+            if (W > 1) __syncthreads();
             if (active) {
-                uint32_t c[4] = {(uint32_t)slot, (uint32_t)(step + kw), d.chain_id, 0u};
-                philox4x32_10(c, key0, key1);
-                p = __umulhi(c[0], d.N);
-                q = __umulhi(c[1], d.N);
-                const SiteCoord sp = site_coord(p, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
-                const SiteCoord sq = site_coord(q, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
+                if (widx != 0) {
+                    ppos = L.rec_pp[rix];
+                    qpos = L.rec_pq[rix];
+                    const uint32_t ab = L.rec_ab[rix];
+                    a = (int)(ab & 0xFFu);
+                    b = (int)((ab >> 8) & 0xFFu);
+                }
+                live = (a != b);
+                const SiteCoord sp = pos_site(d, ppos), sq = pos_site(d, qpos);
                 const int32_t pidp = padded_id(d, sp.cx + h, sp.cy + h, sp.cz + h, sp.b);
                 const int32_t pidq = padded_id(d, sq.cx + h, sq.cy + h, sq.cz + h, sq.b);
-                int bx, by, bz;
-                basis_bits(d.A, sp.b, bx, by, bz);
-                ppos = pack_pos(2 * sp.cx + bx, 2 * sp.cy + by, 2 * sp.cz + bz);
-                basis_bits(d.A, sq.b, bx, by, bz);
-                qpos = pack_pos(2 * sq.cx + bx, 2 * sq.cy + by, 2 * sq.cz + bz);
-                a = load_species<kStore>(L, d, pidp);
-                b = load_species<kStore>(L, d, pidq);
-                live = (a != b);
                 if (live) {
+                    // padded linear deltas of every offset from the two sites' bases
+                    const int32_t *dlp = reinterpret_cast<const int32_t *>(L.dlin4) + sp.b;
+                    const int32_t *dlq = reinterpret_cast<const int32_t *>(L.dlin4) + sq.b;
 #pragma unroll 1
                     for (int s2 = 0; s2 < S; ++s2) {
                         const int t0 = max(g0, (int)d.zstart[s2]), t1 = min(g1, (int)d.zstart[s2 + 1]);
@@ -382,14 +400,11 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                         int t = t0;
 #pragma unroll 1
                         for (; t + kU <= t1; t += kU) {
-                            int4 dl[kU];
-#pragma unroll
-                            for (int u = 0; u < kU; ++u) dl[u] = L.dlin4[t + u];
                             int ap[kU], aq[kU];
 #pragma unroll
                             for (int u = 0; u < kU; ++u) {
-                                ap[u] = pidp + sel4(dl[u], sp.b);
-                                aq[u] = pidq + sel4(dl[u], sq.b);
+                                ap[u] = pidp + dlp[(t + u) * 4];
+                                aq[u] = pidq + dlq[(t + u) * 4];
                             }
                             int vp[kU], vq[kU];
 #pragma unroll
@@ -405,9 +420,8 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                         }
 #pragma unroll 1
                         for (; t < t1; ++t) {
-                            const int4 dl = L.dlin4[t];
-                            hp += one_at<Hist>(load_species<kStore>(L, d, pidp + sel4(dl, sp.b)));
-                            hq += one_at<Hist>(load_species<kStore>(L, d, pidq + sel4(dl, sq.b)));
+                            hp += one_at<Hist>(load_species<kStore>(L, d, pidp + dlp[t * 4]));
+                            hq += one_at<Hist>(load_species<kStore>(L, d, pidq + dlq[t * 4]));
                         }
                         if (bal) {
                             // this wavefront's part of shell s2 (read by its owner when live)
@@ -498,12 +512,6 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                 ((Hist *)L.rec_cp)[k * Bt + rix] = cp;
                 ((Hist *)L.rec_cq)[k * Bt + rix] = cq;
                 L.rec_dQ[k * Bt + rix] = dQ;
-                if (k == 0) {
-                    L.rec_pp[rix] = ppos;
-                    L.rec_pq[rix] = qpos;
-                    L.rec_ab[rix] = (uint32_t)a | ((uint32_t)b << 8) |
-                                    ((uint32_t)(active && !live) << 16) | ((uint32_t)active << 17);
-                }
             }
         }
         __syncthreads();
