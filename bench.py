@@ -14,7 +14,8 @@ Inputs are synthetic, seeded and resident in HBM before the timed region.
 After the timed steps the same 512 chains run once more one after another
 through the single-chain entry point ("plain"), and their final configurations
 must equal the batched ones; then 2,000 jobs are served with Poisson arrivals
-at 70 % of the measured batched capacity (p50/p99 of completion - arrival).
+at 70 % of the measured batched capacity under a 512 MB HBM budget (p50/p99 of
+completion - arrival, and of the wait for admission).
 
 Prints one JSON line: value = trial swaps/s of the single chain; the full
 evaluation's GB/s (with the HBM roofline of its kernel) and the batched
@@ -49,7 +50,7 @@ def parse():
     ap.add_argument("--legs", default="eval,eval3,lat,chain,batch")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (one after another) chains")
     ap.add_argument("--serve-jobs", type=int, default=2000, help="served jobs (0 = skip serving)")
-    ap.add_argument("--serve-budget-mb", type=int, default=64)
+    ap.add_argument("--serve-budget-mb", type=int, default=512)
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered load / batched capacity")
     return ap.parse_args()
 
@@ -143,14 +144,17 @@ def serve(pb, wl, n_jobs, capacity_trials_per_s, load, budget_mb):
         print(f"served jobs failed: {bad[:10]}", file=sys.stderr)
         sys.exit(1)
     sub = np.array([r[3][0] for r in res.values()], dtype=np.float64)
+    adm = np.array([r[3][1] for r in res.values()], dtype=np.float64)
     fin = np.array([r[3][2] for r in res.values()], dtype=np.float64)
     lat = (fin - sub) / 1e6
+    wait = (adm - sub) / 1e6
     trials = sum(r[2]["trials"] for r in res.values())
     span = (fin.max() - sub.min()) / 1e9
     return {"jobs": len(jobs), "offered_jobs_per_s": rate, "offered_load": load,
             "capacity_trials_per_s": capacity_trials_per_s, "hbm_budget_MB": budget_mb,
             "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
-            "latency_ms_max": float(lat.max()), "trials": int(trials), "span_s": span,
+            "latency_ms_max": float(lat.max()), "admission_wait_ms_p50": float(np.percentile(wait, 50)),
+            "admission_wait_ms_p99": float(np.percentile(wait, 99)), "trials": int(trials), "span_s": span,
             "trials_per_s": trials / span, "rounds": c["rounds"], "sites_total": int(sum(j.N for j in jobs))}
 
 

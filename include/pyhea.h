@@ -237,7 +237,9 @@ pyhea_status pyhea_philox4x32_10(const uint32_t *ctr_dev, uint64_t seed, int64_t
  * one wavefront per shell, and the steps per pass.  This switch forces one
  * shape family process-wide: -1 = automatic, 0 = automatic, 1 = LDS nibbles
  * (else HBM), 2 = HBM, 3 = automatic, 4 = offsets spread evenly over the
- * shell wavefronts.  Shapes never change results; EINVAL outside -1..4. */
+ * shell wavefronts, 5 = DISJOINT commits decided one by one, 6 = speculative
+ * commit chunks of 4 candidates.  Shapes never change results; EINVAL outside
+ * -1..6. */
 pyhea_status pyhea_tune_force(int32_t variant);
 
 /* Full-evaluation kernel: -1 = automatic (bit-sliced where it covers the

@@ -42,17 +42,25 @@ LaunchShape choose_launch(const Geometry &g, int B, int lds_budget, int variant,
     const int W = g.S;
     const int bal = variant == 4 && g.S > 1 ? 1 : 0;
     const int kmax = fk > 0 ? fk : std::max(1, std::min(kMaxLookahead, budget / (W * Gs)));
+    // speculative commit chunks: 16 members (8 when a member's table is large),
+    // fewer or none when the LDS is short
+    const int E = g.S * g.M * g.M;
+    int chs[4] = {E <= 128 ? 16 : 8, E <= 128 ? 8 : 4, 4, 0};
+    if (variant == 5) chs[0] = chs[1] = chs[2] = 0;   // commits one by one
+    if (variant == 6) chs[0] = chs[1] = 4;            // small speculative chunks
     for (int si = 0; si < ns; ++si)
         for (int K = kmax; K >= 1; --K) {
             if (mc_block_waves(B, W, K) > 16) continue;
-            for (int bl : {bal, 0}) {
-                const int64_t lds = mc_lds_bytes(g.S, g.M, B, W, bl, K) + species_store_bytes(stores[si], g.Npad);
-                if (lds <= lds_budget) return LaunchShape{stores[si], W, bl, K, (int)lds};
-                if (bal == 0) break;
-            }
+            for (int CH : chs)
+                for (int bl : {bal, 0}) {
+                    const int64_t lds =
+                        mc_lds_bytes(g.S, g.M, B, W, bl, K, CH) + species_store_bytes(stores[si], g.Npad);
+                    if (lds <= lds_budget) return LaunchShape{stores[si], W, bl, K, CH, (int)lds};
+                    if (bal == 0) break;
+                }
         }
     // the HBM store with one step per pass
-    return LaunchShape{kStoreGlobal, W, 0, 1, mc_lds_bytes(g.S, g.M, B, W, 0, 1)};
+    return LaunchShape{kStoreGlobal, W, 0, 1, 0, mc_lds_bytes(g.S, g.M, B, W, 0, 1, 0)};
 }
 
 int forced_variant() {

@@ -16,6 +16,7 @@ struct LaunchShape {
     int W;
     int bal;
     int K;
+    int CH;   // speculative commit chunk (0: commits one by one)
     int lds;
 };
 
@@ -23,11 +24,13 @@ struct LaunchShape {
 // each wavefront gathers its own shell's offsets); 1 = LDS nibbles when they
 // fit, else HBM; 2 = always HBM; 3 = the automatic shape (kept as an explicit
 // name); 4 = automatic store, every wavefront of a slot group gathers an equal
-// share of all offsets and the shells' partial histograms meet in LDS.  The block size follows the
+// share of all offsets and the shells' partial histograms meet in LDS;
+// 5 = the automatic shape with DISJOINT commits decided one by one; 6 = the
+// automatic shape with speculative commit chunks of 4.  The block size follows the
 // number of chains launched together (n_chains) so that all can be resident;
 // the steps per pass are the largest (up to 4) that fit it, unless forced.
 // Every variant gives bit-identical results.
-constexpr int kNumStoreVariants = 5;
+constexpr int kNumStoreVariants = 7;
 
 LaunchShape choose_launch(const Geometry &g, int B, int lds_budget, int variant, int n_chains);
 int wave_budget(int n_chains);

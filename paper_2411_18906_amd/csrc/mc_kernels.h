@@ -7,15 +7,12 @@
 
 namespace pyhea {
 
-// Members of the conflict-free set evaluated together by the speculative commit
-// phase (E = S M M entries per member).
-__host__ __device__ inline int spec_chunk(int E) { return E <= 128 ? 16 : 8; }
-
 // LDS layout of the MC kernel (must match the carve order in mc_kernels.hip).
 // W = wavefronts per slot group (>= S), bal = offsets spread evenly over them
 // (partial histograms exchanged through LDS), K = steps whose candidates one
-// pass evaluates (records for K * B slots).
-__host__ __device__ inline int mc_lds_bytes(int S, int M, int B, int W = 0, int bal = 0, int K = 1) {
+// pass evaluates (records for K * B slots), CH = members of the conflict-free
+// set the speculative commit phase evaluates together (0: one by one; <= 16).
+__host__ __device__ inline int mc_lds_bytes(int S, int M, int B, int W = 0, int bal = 0, int K = 1, int CH = 0) {
     auto r = [](int b) { return (b + 15) & ~15; };
     const int E = S * M * M;
     const int Bt = K * B;
@@ -28,7 +25,7 @@ __host__ __device__ inline int mc_lds_bytes(int S, int M, int B, int W = 0, int 
     n += 2 * r(Bt * 4);                           // order, list (per step of a pass)
     n += r(2 * kMaxShells * 8) + r(32 * 4);       // sh_dQ (two buffers), sh_int
     if (bal) n += r(S * W * 2 * Bt * (M > 6 ? 8 : 4));  // partial histograms
-    n += r(64 * 8) + r(spec_chunk(E) * E * 8) + r(16 * kMaxShells * 8);  // speculative commits
+    if (CH > 0) n += r(64 * 8) + r(CH * E * 8) + r(CH * E * 4) + r(16 * kMaxShells * 8) + r(16 * 4) + r(4 * 4);
     return n;
 }
 
@@ -46,7 +43,7 @@ constexpr int kMaxLookahead = 8;
 
 // One launch of n_chains chains (one block each) for up to max_steps steps.
 hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M, int S, int B, int W, int bal,
-                     int K, int lds_bytes, int max_steps, hipStream_t stream);
+                     int K, int CH, int lds_bytes, int max_steps, hipStream_t stream);
 hipError_t launch_pad_fill(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);
 hipError_t launch_pad_drain(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);
 // out[i] = *descs_dev[i].state (device array of n_chains states).

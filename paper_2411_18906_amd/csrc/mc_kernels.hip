@@ -81,7 +81,10 @@ struct Lds {
     void *part;         // [S][W][2 (cp, cq)][K B] partial histograms (bal)
     uint64_t *spec_cm;  // [64] earlier candidates each improving candidate conflicts with
     double *spec_T;     // [CH][E] change of every entry's term under each member of a chunk
+    int32_t *spec_P;    // [CH][E] change of every entry's count after each member
     double *spec_Q;     // [16][kMaxShells] dQ_k of each member of a chunk
+    int32_t *spec_mem;  // [16] slots of a chunk's members
+    int32_t *spec_ctl;  // [4] members in the current chunk
     uint8_t *store;     // species store
 };
 
@@ -207,6 +210,15 @@ __device__ __forceinline__ int entry_dn(const Lds &L, int Bt, int r, int k, int 
     return __mul24(ui, fld(cq, j) - fld(cp, j)) + __mul24(uj, fld(cq, i) - fld(cp, i));
 }
 
+// inclusive prefix sum along each 16-lane row (lanes outside the row read 0)
+__device__ __forceinline__ int row_prefix_sum(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, true);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, true);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, true);  // row_shr:8
+    return x;
+}
+
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
     const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
     const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
@@ -215,7 +227,7 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
 
 template <int kStore, int M>
 __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ descs,
-                                                  int32_t max_steps, int32_t W, int32_t bal, int32_t K) {
+                                                  int32_t max_steps, int32_t W, int32_t bal, int32_t K, int32_t CH) {
     using Hist = typename HistT<(M > 6)>::type;
     const ChainDesc &d = descs[blockIdx.x];
     ChainState *st = d.state;
@@ -257,9 +269,14 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
         L.sh_dQ = (double *)carve(p, 2 * kMaxShells * 8);
         L.sh_int = (int32_t *)carve(p, 32 * 4);
         if (bal) L.part = carve(p, S * W * 2 * Bt * (int)sizeof(Hist));
-        L.spec_cm = (uint64_t *)carve(p, kWave * 8);
-        L.spec_T = (double *)carve(p, spec_chunk(E) * E * 8);
-        L.spec_Q = (double *)carve(p, 16 * kMaxShells * 8);
+        if (CH > 0) {
+            L.spec_cm = (uint64_t *)carve(p, kWave * 8);
+            L.spec_T = (double *)carve(p, CH * E * 8);
+            L.spec_P = (int32_t *)carve(p, CH * E * 4);
+            L.spec_Q = (double *)carve(p, 16 * kMaxShells * 8);
+            L.spec_mem = (int32_t *)carve(p, 16 * 4);
+            L.spec_ctl = (int32_t *)carve(p, 4 * 4);
+        }
         L.store = p;
     }
 
@@ -622,7 +639,7 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
         // per re-validated candidate to add the shells' dQ.  Site writes wait
         // until the end of the phase: later candidates never read committed sites.
         int n_commit = 0;
-        const bool spec = d.mode == PYHEA_MODE_DISJOINT && n_impr >= 3 && n_impr <= kWave;
+        const bool spec = CH > 0 && d.mode == PYHEA_MODE_DISJOINT && n_impr >= 3 && n_impr <= kWave;
         if (spec) {
             // The same rule, evaluated speculatively.  cm[u] marks the earlier
             // candidates that candidate u conflicts with.  The greedy conflict-free
@@ -630,7 +647,6 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
             // counts as if every member commits, CH members at a time; members
             // before the first one that fails re-validation commit, exactly as they
             // would one by one, and the search resumes after the failed member.
-            const int CH = spec_chunk(E);
             const int nwaves = nthreads / kWave;
             for (int u = wave; u < n_impr; u += nwaves) {
                 const int su = L.order[rb + u];
@@ -646,101 +662,109 @@ __global__ void __launch_bounds__(1024) mc_kernel(const ChainDesc *__restrict__ 
                 if (lane == 0) L.spec_cm[u] = mk;
             }
             __syncthreads();
-            const uint64_t my_cm = lane < n_impr ? L.spec_cm[lane] : 0ull;
-            const bool own = (int)threadIdx.x < E;   // this thread's entry of the counts
-            const int e = threadIdx.x;
-            const int ek = own ? e / (M * M) : 0, ei = own ? (e / M) % M : 0, ej = own ? e % M : 0;
-            uint64_t committed = 0;
-            int next = 0;
-            while (next < n_impr) {
-                uint64_t I = 0;
-                for (int u = next; u < n_impr; ++u)
-                    if ((readlane_u64(my_cm, u) & (committed | I)) == 0) I |= 1ull << u;
-                int fail_u = -1;
-                while (I) {
-                    uint64_t chunk = 0;
-                    int m = 0;
-                    for (uint64_t t2 = I; t2 && m < CH; t2 &= t2 - 1, ++m) chunk |= t2 & (~t2 + 1ull);
-                    // every entry's term change under each member, in rank order
-                    int cnt0 = 0, run = 0;
-                    double Rv = 0.0, tv = 0.0;
-                    if (own) {
+            // The search state (committed candidates, the current conflict-free set,
+            // the next undecided rank) lives in wavefront 0, which hands each chunk's
+            // members to the others through LDS: the scalar work runs once, not once
+            // per wavefront on the CU's shared scalar unit.
+            const uint64_t my_cm = wave == 0 && lane < n_impr ? L.spec_cm[lane] : 0ull;
+            uint64_t committed = 0, I = 0, chunk = 0;
+            int next = 0, my_s = 0;
+            for (;;) {
+                if (wave == 0) {
+                    if (I == 0 && next < n_impr) {
+                        for (int u = next; u < n_impr; ++u)
+                            if ((readlane_u64(my_cm, u) & (committed | I)) == 0) I |= 1ull << u;
+                        next = n_impr;
+                    }
+                    // the next CH members; lane vi < m holds member vi's slot
+                    chunk = 0;
+                    int m = 0, my_u = 0;
+                    for (uint64_t t2 = I; t2 && m < CH; t2 &= t2 - 1, ++m) {
+                        const uint64_t low = t2 & (~t2 + 1ull);
+                        chunk |= low;
+                        if (lane == m) my_u = __ffsll((long long)low) - 1;
+                    }
+                    my_s = lane < m ? L.order[rb + my_u] : 0;
+                    if (lane < m) L.spec_mem[lane] = my_s;
+                    if (lane == 0) L.spec_ctl[0] = m;
+                }
+                __syncthreads();
+                const int m = L.spec_ctl[0];
+                if (m == 0) break;
+                // each entry's count change under each member: the members of a chunk
+                // lie along a 16-lane row, an inclusive prefix of the changes gives
+                // the counts before each member, then the member's term change
+                for (int eb = wave * 4; eb < E; eb += nwaves * 4) {
+                    const int e = eb + (lane >> 4), vi = lane & 15;
+                    const bool valid = e < E && vi < m;
+                    int dn = 0;
+                    if (valid) dn = entry_dn<M, Hist>(L, Bt, rb + L.spec_mem[vi], e / (M * M), (e / M) % M, e % M);
+                    const int incl = row_prefix_sum(dn);
+                    if (valid) {
                         const Ent en = L.ent[e];
-                        cnt0 = run = en.cnt;
-                        Rv = en.R;
-                        tv = en.t;
-                        int vi = 0;
-                        for (uint64_t t2 = chunk; t2; t2 &= t2 - 1, ++vi) {
-                            const int r = rb + L.order[rb + __ffsll((long long)t2) - 1];
-                            const int dn = entry_dn<M, Hist>(L, Bt, r, ek, ei, ej);
-                            double delta = 0.0;
-                            if (dn != 0) {
-                                delta = sq_dev(run + dn, Rv, tv) - sq_dev(run, Rv, tv);
-                                run += dn;
-                            }
-                            L.spec_T[vi * E + e] = delta;
-                        }
+                        const int before = en.cnt + incl - dn;
+                        double delta = 0.0;
+                        if (dn != 0) delta = sq_dev(before + dn, en.R, en.t) - sq_dev(before, en.R, en.t);
+                        L.spec_T[vi * E + e] = delta;
+                        L.spec_P[vi * E + e] = incl;
                     }
-                    __syncthreads();
-                    // dQ_k per member: rows in order, each row's terms in order (terms
-                    // of unchanged entries are exactly +0.0)
-                    for (int it = threadIdx.x; it < m * S; it += nthreads) {
-                        const int vi = it / S, kk = it - vi * S;
-                        const double *T = L.spec_T + vi * E + kk * M * M;
-                        double Q = 0.0;
+                }
+                __syncthreads();
+                // dQ_k per member: rows in order, each row's terms in order (terms
+                // of unchanged entries are exactly +0.0)
+                for (int it = threadIdx.x; it < m * S; it += nthreads) {
+                    const int vi = it / S, kk = it - vi * S;
+                    const double *T = L.spec_T + vi * E + kk * M * M;
+                    double Q = 0.0;
 #pragma unroll
-                        for (int i = 0; i < M; ++i) {
-                            double rs = 0.0;
+                    for (int i = 0; i < M; ++i) {
+                        double rs = 0.0;
 #pragma unroll
-                            for (int j = 0; j < M; ++j) rs = rs + T[i * M + j];
-                            Q = Q + rs;
-                        }
-                        L.spec_Q[vi * kMaxShells + kk] = Q;
+                        for (int j = 0; j < M; ++j) rs = rs + T[i * M + j];
+                        Q = Q + rs;
                     }
-                    __syncthreads();
-                    // the first member whose dS fails (the step's first commit is not
-                    // re-validated); every wavefront finds the same one
-                    bool fails = false;
-                    if (lane < m) {
-                        double dS = 0.0;
+                    L.spec_Q[vi * kMaxShells + kk] = Q;
+                }
+                __syncthreads();
+                // the first member whose dS fails (the step's first commit is not
+                // re-validated); every wavefront finds the same one
+                bool fails = false;
+                if (lane < m) {
+                    double dS = 0.0;
 #pragma unroll
-                        for (int kk = 0; kk < kMaxShells; ++kk)
-                            if (kk < S) dS = dS + wk[kk] * L.spec_Q[lane * kMaxShells + kk];
-                        fails = !(dS < -tau) && !(n_commit == 0 && lane == 0);
-                    }
-                    const uint64_t fm = ballot64(fails);
-                    const int f = fm ? __ffsll((long long)fm) - 1 : m;
-                    if (own) {
-                        int r2 = run;
-                        if (f < m) {
-                            r2 = cnt0;
-                            int vi = 0;
-                            for (uint64_t t2 = chunk; t2 && vi < f; t2 &= t2 - 1, ++vi)
-                                r2 += entry_dn<M, Hist>(L, Bt, rb + L.order[rb + __ffsll((long long)t2) - 1], ek, ei, ej);
-                        }
-                        if (r2 != cnt0) {
+                    for (int kk = 0; kk < kMaxShells; ++kk)
+                        if (kk < S) dS = dS + wk[kk] * L.spec_Q[lane * kMaxShells + kk];
+                    fails = !(dS < -tau) && !(n_commit == 0 && lane == 0);
+                }
+                const uint64_t fm = ballot64(fails);
+                const int f = fm ? __ffsll((long long)fm) - 1 : m;
+                // members [0, f) commit: counts after member f - 1, their squared
+                // deviations, and the list of committed slots
+                if (f > 0)
+                    for (int e = threadIdx.x; e < E; e += nthreads) {
+                        const int dsum = L.spec_P[(f - 1) * E + e];
+                        if (dsum != 0) {
                             Ent en = L.ent[e];
-                            en.cnt = r2;
-                            en.sq = sq_dev(r2, Rv, tv);
+                            en.cnt += dsum;
+                            en.sq = sq_dev(en.cnt, en.R, en.t);
                             L.ent[e] = en;
                         }
                     }
-                    {
-                        int vi = 0;
-                        uint64_t t2 = chunk;
-                        for (; vi < f; t2 &= t2 - 1, ++vi) {
-                            const int u = __ffsll((long long)t2) - 1;
-                            if (threadIdx.x == 0) L.list[n_commit + vi] = L.order[rb + u];
-                            committed |= 1ull << u;
-                        }
-                        if (f < m) fail_u = __ffsll((long long)t2) - 1;
+                if (wave == 0) {
+                    if (lane < f) L.list[n_commit + lane] = my_s;
+                    uint64_t t2 = chunk;
+                    for (int vi = 0; vi < f; ++vi) {
+                        committed |= t2 & (~t2 + 1ull);
+                        t2 &= t2 - 1;
                     }
-                    n_commit += f;
                     I &= ~chunk;
-                    __syncthreads();
-                    if (f < m) break;
+                    if (f < m) {
+                        // resume after the member that failed, with a new conflict-free set
+                        next = __ffsll((long long)t2);
+                        I = 0;
+                    }
                 }
-                next = fail_u >= 0 ? fail_u + 1 : n_impr;
+                n_commit += f;
             }
         }
         int n_meet = 0;
@@ -935,8 +959,9 @@ const void *mc_fn(int M) {
 }
 
 hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M, int S, int B, int W, int bal,
-                     int K, int lds_bytes, int max_steps, hipStream_t stream) {
-    if (mc_block_threads(B, W, K) > 1024 || K < 1 || K > kMaxLookahead || W < S || (!bal && W != S))
+                     int K, int CH, int lds_bytes, int max_steps, hipStream_t stream) {
+    if (mc_block_threads(B, W, K) > 1024 || K < 1 || K > kMaxLookahead || W < S || (!bal && W != S) || CH < 0 ||
+        CH > 16)
         return hipErrorInvalidValue;
     const dim3 grid(n_chains), block(mc_block_threads(B, W, K));
     const void *fn = store == kStoreLds8 ? mc_fn<kStoreLds8>(M)
@@ -944,7 +969,7 @@ hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M,
                                            : mc_fn<kStoreGlobal>(M);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (e != hipSuccess) return e;
-    void *args[] = {(void *)&descs_dev, (void *)&max_steps, (void *)&W, (void *)&bal, (void *)&K};
+    void *args[] = {(void *)&descs_dev, (void *)&max_steps, (void *)&W, (void *)&bal, (void *)&K, (void *)&CH};
     return hipLaunchKernel(fn, grid, block, args, (size_t)lds_bytes, stream);
 }
 

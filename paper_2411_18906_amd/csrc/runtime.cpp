@@ -298,7 +298,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
     for (int c = 0; c < n; ++c)
         std::memcpy(hy_at(o_target) + eoff[c] * 8, jobs[c].target.data(), jobs[c].target.size() * 8);
     std::vector<ChainDesc> descs(n);
-    std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<int>> groups;
+    std::map<std::tuple<int, int, int, int, int, int, int, int>, std::vector<int>> groups;
     for (int c = 0; c < n; ++c) {
         const ChainJob &j = jobs[c];
         ChainDesc &d = descs[c];
@@ -323,10 +323,10 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         d.store = shape[c].store;
         d.lds_bytes = shape[c].lds;
         d.sym = symmetric_target(j.target.data(), j.g.S, j.g.M);
-        groups[{shape[c].store, j.g.M, j.g.S, d.B, shape[c].W, shape[c].bal, shape[c].K}].push_back(c);
+        groups[{shape[c].store, j.g.M, j.g.S, d.B, shape[c].W, shape[c].bal, shape[c].K, shape[c].CH}].push_back(c);
     }
     struct Launch {
-        int first, count, store, M, S, B, W, bal, K, lds;
+        int first, count, store, M, S, B, W, bal, K, CH, lds;
     };
     std::vector<Launch> launches;
     {
@@ -347,6 +347,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
                      std::get<4>(kv.first),
                      std::get<5>(kv.first),
                      std::get<6>(kv.first),
+                     std::get<7>(kv.first),
                      0};
             for (int c : idx) {
                 L.lds = std::max(L.lds, descs[c].lds_bytes);
@@ -412,7 +413,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
             hipStream_t s = fork.stream((int)l);
             if (L.store == kStoreGlobal) PYHEA_HIP(launch_pad_fill(ddev + L.first, L.count, s));
             PYHEA_HIP(
-                launch_mc(ddev + L.first, L.count, L.store, L.M, L.S, L.B, L.W, L.bal, L.K, L.lds, INT_MAX, s));
+                launch_mc(ddev + L.first, L.count, L.store, L.M, L.S, L.B, L.W, L.bal, L.K, L.CH, L.lds, INT_MAX, s));
             if (L.store == kStoreGlobal) PYHEA_HIP(launch_pad_drain(ddev + L.first, L.count, s));
         }
         PYHEA_HIP(fork.end());

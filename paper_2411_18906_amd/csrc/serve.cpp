@@ -96,7 +96,7 @@ struct Job {
     ChainDesc desc{};
     int store = kStoreLds8;
     int lds = 0;
-    int W = 1, bal = 0, K = 1;
+    int W = 1, bal = 0, K = 1, CH = 0;
     JobLayout lay{};
 };
 
@@ -350,9 +350,9 @@ void Server::run() {
             continue;
         }
         // one round: group by launch shape, one stream per group
-        std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<Job *>> groups;
+        std::map<std::tuple<int, int, int, int, int, int, int, int>, std::vector<Job *>> groups;
         for (Job *j : run_set)
-            groups[{j->store, j->g.M, j->g.S, j->params.cand_per_step, j->W, j->bal, j->K}].push_back(j);
+            groups[{j->store, j->g.M, j->g.S, j->params.cand_per_step, j->W, j->bal, j->K, j->CH}].push_back(j);
         std::vector<ChainDesc> descs;
         std::vector<Job *> order;
         std::vector<std::pair<size_t, std::vector<Job *>>> launches;
@@ -376,7 +376,8 @@ void Server::run() {
             hipStream_t s = streams[gi % streams.size()];
             ok = s == s0 || hipStreamWaitEvent(s, ready, 0) == hipSuccess;
             ok = ok && launch_mc((const ChainDesc *)desc_dev + L.first, (int)L.second.size(), j0->store, j0->g.M,
-                                 j0->g.S, j0->params.cand_per_step, j0->W, j0->bal, j0->K, lds, steps_per_round,
+                                 j0->g.S, j0->params.cand_per_step, j0->W, j0->bal, j0->K, j0->CH, lds,
+                                 steps_per_round,
                                  s) == hipSuccess;
         }
         for (size_t i = 0; i < streams.size(); ++i) ok = ok && hipStreamSynchronize(streams[i]) == hipSuccess;
@@ -529,6 +530,7 @@ pyhea_status pyhea_serve_submit(void *server, uint64_t job_id, const pyhea_latti
     j->lds = ls.lds;
     j->W = ls.W;
     j->bal = ls.bal;
+    j->CH = ls.CH;
     j->K = ls.K;
     j->footprint = job_footprint(g, j->store);
     std::lock_guard<std::mutex> lk(s->mu);

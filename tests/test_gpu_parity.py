@@ -216,7 +216,7 @@ def test_mc_zero_and_partial_budgets():
         assert_same_chain(o, g)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 def test_store_variants_are_bit_identical(variant):
     lattice, L, M, S = orc.FCC, (6, 6, 6), 5, 3
     rng = np.random.default_rng(5)
@@ -239,7 +239,7 @@ LOOKAHEAD_CASES = [
 ]
 
 
-@pytest.mark.parametrize("K,variant", [(1, 0), (2, 0), (3, 0), (5, 0), (8, 0), (2, 4), (5, 4)])
+@pytest.mark.parametrize("K,variant", [(1, 0), (2, 0), (3, 0), (5, 0), (8, 0), (2, 4), (5, 4), (3, 5), (4, 6)])
 @pytest.mark.parametrize("case", LOOKAHEAD_CASES)
 def test_lookahead_is_bit_identical(case, K, variant):
     lattice, L, M, S, B, mode, T, depth, zero = case
