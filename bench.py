@@ -292,7 +292,7 @@ def main():
         alg_bytes = K * (N + S * M * M * 4 + 16)
         gbps = alg_bytes / (ms.mean() / 1e3) / 1e9
         out["sro_eval"] = {"GBps": gbps, "configs_per_s": K / (ms.mean() / 1e3), "ms": float(ms.mean()),
-                           "frac_hbm": gbps / HBM_PEAK_GBPS}
+                           "ms_steps": [round(float(x), 4) for x in ms], "frac_hbm": gbps / HBM_PEAK_GBPS}
         tb = recorded_traffic()
         out["roofline"] = {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                            "frac": gbps / HBM_PEAK_GBPS,

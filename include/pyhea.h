@@ -243,8 +243,11 @@ pyhea_status pyhea_philox4x32_10(const uint32_t *ctr_dev, uint64_t seed, int64_t
 pyhea_status pyhea_tune_force(int32_t variant);
 
 /* Full-evaluation kernel: -1 = automatic (bit-sliced where it covers the
- * geometry, else gather), 0 = gather, 1 = bit-sliced where possible.  Both
- * give identical counts. */
+ * geometry, else gather), 0 = gather, 1 = bit-sliced where possible (a
+ * configuration whose layers would take more than half of a CU's LDS is cut
+ * along z so that two workgroups share each CU), 2 = bit-sliced without that
+ * cut, 3 = bit-sliced cut for four workgroups per CU.  All give identical
+ * counts. */
 pyhea_status pyhea_tune_force_eval(int32_t kernel);
 
 /* Steps whose candidates one pass of the MC kernel evaluates at once: 0 =

@@ -62,7 +62,7 @@ pyhea_status pyhea_sro_eval(const pyhea_lattice *lat, const int8_t *species_dev,
     const int E = g.S * g.M * g.M;
     AsyncBuffer buf;
     buf.stream = stream;
-    PYHEA_HIP(hipMallocAsync(&buf.ptr, E * 4 + 256, stream));
+    PYHEA_HIP(pool_alloc(&buf.ptr, E * 4 + 256, stream));
     int32_t *counts = (int32_t *)buf.ptr;
     int32_t *bad = (int32_t *)((char *)buf.ptr + ((E * 4 + 127) & ~127));
     {
@@ -119,7 +119,7 @@ pyhea_status pyhea_sro_eval_batch(const pyhea_lattice *lat, int64_t n_configs, c
     buf.stream = stream;
     const size_t bad_bytes = (size_t)n_configs * 4;
     const size_t tw_off = (bad_bytes + 255) & ~size_t(255);
-    PYHEA_HIP(hipMallocAsync(&buf.ptr, tw_off + (E + kMaxShells) * 8, stream));
+    PYHEA_HIP(pool_alloc(&buf.ptr, tw_off + (E + kMaxShells) * 8, stream));
     int32_t *bad = (int32_t *)buf.ptr;
     double *tdev = (double *)((char *)buf.ptr + tw_off);
     EvalDesc ed;
@@ -160,7 +160,7 @@ pyhea_status pyhea_trial_eval(const pyhea_lattice *lat, const pyhea_objective *o
     const int E = g.S * g.M * g.M;
     AsyncBuffer buf;
     buf.stream = stream;
-    PYHEA_HIP(hipMallocAsync(&buf.ptr, 256 + E * 4 + (E + kMaxShells) * 8 + 256, stream));
+    PYHEA_HIP(pool_alloc(&buf.ptr, 256 + E * 4 + (E + kMaxShells) * 8 + 256, stream));
     int32_t *bad = (int32_t *)buf.ptr;
     int32_t *counts = (int32_t *)((char *)buf.ptr + 256);
     double *tdev = (double *)((char *)buf.ptr + 256 + ((E * 4 + 255) & ~255));
@@ -273,8 +273,9 @@ pyhea_status pyhea_philox4x32_10(const uint32_t *ctr_dev, uint64_t seed, int64_t
 }
 
 pyhea_status pyhea_tune_force_eval(int32_t kernel) {
-    if (kernel < -1 || kernel > 1) {
-        set_error("kernel must be -1 (automatic), 0 (gather) or 1 (bit-sliced)");
+    if (kernel < -1 || kernel > 3) {
+        set_error("kernel must be -1 (automatic), 0 (gather), 1 (bit-sliced), 2 (bit-sliced, no z split) or 3 "
+                  "(bit-sliced, four workgroups per CU)");
         return PYHEA_EINVAL;
     }
     set_forced_eval_kernel(kernel);

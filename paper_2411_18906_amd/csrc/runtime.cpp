@@ -25,6 +25,25 @@ pyhea_status device_error(hipError_t e, const char *what) {
     return PYHEA_EDEVICE;
 }
 
+hipError_t pool_alloc(void **ptr, size_t bytes, hipStream_t stream) {
+    static std::mutex mu;
+    static bool tuned[64] = {false};
+    int dev = 0;
+    hipError_t r = hipGetDevice(&dev);
+    if (r != hipSuccess) return r;
+    if (dev >= 0 && dev < 64) {
+        std::lock_guard<std::mutex> lock(mu);
+        if (!tuned[dev]) {
+            hipMemPool_t pool;
+            if ((r = hipDeviceGetDefaultMemPool(&pool, dev)) != hipSuccess) return r;
+            uint64_t keep = kPoolRetainBytes;
+            if ((r = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep)) != hipSuccess) return r;
+            tuned[dev] = true;
+        }
+    }
+    return hipMallocAsync(ptr, bytes, stream);
+}
+
 int max_lds_per_block() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
@@ -138,9 +157,10 @@ pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, 
     if (K <= 0) return PYHEA_OK;
     const int forced = forced_eval_kernel();
     BitDesc bd;
-    if (forced != 0 && fill_bit_desc(g, max_lds_per_block(), K, &bd)) {
+    const int split = forced == 2 ? 1 : forced == 3 ? 4 : 2;
+    if (forced != 0 && fill_bit_desc(g, max_lds_per_block(), K, split, &bd)) {
         void *partial = nullptr;
-        if (bd.nchunks > 1) PYHEA_HIP(hipMallocAsync(&partial, (size_t)K * bd.partial_stride * 4, stream));
+        if (bd.nchunks > 1) PYHEA_HIP(pool_alloc(&partial, (size_t)K * bd.partial_stride * 4, stream));
         const bool fuse = S_F != nullptr;   // the counting launch finishes Eq. 2-3 too
         const hipError_t e = launch_count_bits(g, bd, K, species, (int32_t *)partial, counts, bad,
                                                fuse ? tw : nullptr, fuse ? S_F : nullptr, stream);
@@ -157,10 +177,12 @@ pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, 
 
 namespace {
 
+// Stream-ordered allocation, freed on the same stream.
 struct DeviceBuffer {
     void *ptr = nullptr;
+    hipStream_t stream = nullptr;
     ~DeviceBuffer() {
-        if (ptr) (void)hipFree(ptr);
+        if (ptr) (void)hipFreeAsync(ptr, stream);
     }
 };
 
@@ -195,6 +217,9 @@ struct Fork {
     int used = 0;
     std::vector<hipEvent_t> events;
     ~Fork() {
+        // left without end() on an error path: let the aux streams drain before
+        // anything they read is released on the caller's stream
+        for (int i = 0; i < used; ++i) (void)hipStreamSynchronize(aux[i]);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
     }
     // launch i goes to the caller's stream (i % (used + 1) == 0) or aux stream
@@ -289,7 +314,8 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         }
     }
     DeviceBuffer arena;
-    PYHEA_HIP(hipMalloc(&arena.ptr, off));
+    arena.stream = stream;
+    PYHEA_HIP(pool_alloc(&arena.ptr, off, stream));
     char *base = (char *)arena.ptr;
 
     // block Y on the host: targets, chain descriptors (ordered by launch group), count tasks

@@ -20,6 +20,12 @@ pyhea_status device_error(hipError_t e, const char *what);
         if (_e != hipSuccess) return device_error(_e, #expr); \
     } while (0)
 
+// Stream-ordered allocation from the current device's default pool.  The first
+// call on a device makes the pool keep up to kPoolRetainBytes of freed memory
+// across synchronisations, so that repeated calls do not map and unmap pages.
+constexpr uint64_t kPoolRetainBytes = uint64_t(2) << 30;
+hipError_t pool_alloc(void **ptr, size_t bytes, hipStream_t stream);
+
 // Largest dynamic LDS one workgroup may allocate on the current device.
 int max_lds_per_block();
 

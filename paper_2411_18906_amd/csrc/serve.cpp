@@ -195,7 +195,7 @@ std::vector<bool> Server::admit(const std::vector<Job *> &js, hipStream_t s) {
         Job *j = js[i];
         const Geometry &g = j->g;
         j->lay = job_layout(g, j->store);
-        if (hipMallocAsync(&j->mem, j->lay.total, s) != hipSuccess) {
+        if (pool_alloc(&j->mem, j->lay.total, s) != hipSuccess) {
             j->mem = nullptr;
             continue;
         }

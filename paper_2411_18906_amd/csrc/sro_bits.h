@@ -14,7 +14,7 @@ struct BitDesc {
     int32_t PADW;      // zero words before and after each plane
     int32_t PW;        // LW + 2 * PADW
     int32_t cw0, NCW;  // words that hold centre sites
-    int32_t nchx;      // 32-cell chunks per row
+    int32_t nchx;      // 32-position chunks per padded row (RS bits)
     int32_t ZC;        // centre layers per workgroup
     int32_t nchunks;   // workgroups per configuration
     int32_t threads;   // workgroup size
@@ -23,14 +23,16 @@ struct BitDesc {
     int32_t nh;
     int32_t hstart[kMaxShells + 1];
     int32_t zk[kMaxShells];
-    int32_t tab_delta[4][kMaxOffsets / 2];  // neighbour plane word offset per (basis, half offset)
+    int32_t tab_delta[4][kMaxOffsets / 2];  // neighbour dword offset per (basis, half offset)
     int32_t tab_r[4][kMaxOffsets / 2];      // funnel-shift amount
 };
 
 // Fills bd; false if the bit-sliced kernel does not cover this geometry.
 // K is the number of configurations of the launch: few configurations are
-// split along z over more workgroups.
-bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, BitDesc *bd);
+// split along z over more workgroups.  With split > 1, a configuration whose
+// layers would take more than 1/split of a CU's LDS is cut along z so that
+// `split` workgroups share each CU.
+bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitDesc *bd);
 
 // counts [K][S][M][M] and bad [K] of K configurations; `partial` is scratch of
 // K * bd.partial_stride int32 (used when a configuration spans several

@@ -1,20 +1,24 @@
 // Bit-sliced full SRO evaluation for FCC supercells (Sec. 4.3, Eq. 2).
 //
 // One workgroup counts a range of z-layers of one configuration:
-//  1. Conversion.  Each FCC cell is one dword (4 sublattice bytes).  A v_perm
-//     lookup table maps species ids to one-hot bits; 8 cells are merged per
-//     byte lane with shift-or and a 4x4 byte transpose yields, per sublattice b
-//     and species j < M-1, a 32-cell bit row.  Rows are OR-ed into a flat bit
-//     array per (layer, b, j) with a one-cell periodic border:
-//     bit = (cy + 1) * (Lx + 2) + (cx + 1).
-//  2. Counting.  For a half-offset d (one of each +-d pair) from sublattice b
-//     to b' with cell delta (dx, dy, dz), the neighbour bits of a 32-bit word
-//     are a funnel shift by dy*(Lx+2)+dx of plane (layer+dz, b', j).  With
-//     P_i the centre planes and Q_j the shifted ones,
-//        T_d[i][i] = 2 popc(P_i & Q_i),
-//        T_d[i][j] = popc((P_i & Q_j) | (P_j & Q_i))     (i < j < M-1)
-//     (the two sets are disjoint), and T_d = H_d + H_d^T.  Rows of T_d sum to
-//     2 n_i, so entries involving species M-1 follow from the others.
+//  1. Conversion.  Per sublattice b and species j < M-1 a layer becomes a flat
+//     bit array with a one-cell periodic border: bit fy * RS + fx (RS = Lx + 2)
+//     holds cell ((fx - 1) mod Lx, (fy - 1) mod Ly).  A lane converts one padded
+//     row: each FCC cell is one dword (4 sublattice bytes), a v_perm lookup maps
+//     species ids to one-hot bytes, 8 cells are merged per byte lane with
+//     shift-or, and a 4x4 byte transpose yields 32-position bit rows that are
+//     OR-ed into LDS.  The M-1 species planes are interleaved word by word:
+//     dword ((layer * 4 + b) * PW + word) * (M - 1) + j.
+//  2. Counting.  For a half-offset d (one of each +-d pair) from sublattice b to
+//     b' with cell delta (dx, dy, dz), the neighbour bits of a 32-bit word are a
+//     funnel shift by dy*RS+dx of plane (layer+dz, b', j).  With P_i the centre
+//     planes and Q_j the shifted ones (each set pairwise disjoint),
+//        D_i  = popc(P_i & Q_i),
+//        U_ij = popc((P_i | P_j) & (Q_i | Q_j))
+//             = D_i + D_j + popc(P_i & Q_j) + popc(P_j & Q_i)        (i < j),
+//     so T_d = H_d + H_d^T has T_d[i][i] = 2 D_i and T_d[i][j] = U_ij - D_i - D_j.
+//     Rows of T_d sum to 2 n_i, so entries involving species M-1 follow from
+//     the others.
 //  3. Finalisation.  N_k = sum over the shell's half-offsets of T_d.
 // Counts are exact integers; invalid ids are detected per configuration.
 #include <hip/hip_runtime.h>
@@ -35,19 +39,13 @@ template <int M>
 struct Pairs {
     static constexpr int P = M - 1;                 // explicit planes
     static constexpr int NP = P * (P + 1) / 2;      // i <= j < M-1
+    // position of (i, j), i <= j, in the per-shell sums: (0,0), (0,1), ..., (1,1), ...
+    static constexpr __host__ __device__ int q(int i, int j) { return i * P - i * (i - 1) / 2 + (j - i); }
 };
 
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
     return __builtin_amdgcn_perm(hi, lo, sel);
 }
-
-__device__ __forceinline__ void or_row(uint32_t *plane, int o, uint32_t r) {
-    const int w = o >> 5, s = o & 31;
-    atomicOr(&plane[w], r << s);
-    if (s) atomicOr(&plane[w + 1], r >> (32 - s));
-}
-
-__device__ __forceinline__ void or_bit(uint32_t *plane, int o) { atomicOr(&plane[o >> 5], 1u << (o & 31)); }
 
 // Sum over the 64 lanes of a wave, valid in lane 63: quad swaps, half-row and
 // row mirrors, then row broadcasts 15 and 31 (DPP; no LDS traffic).
@@ -64,11 +62,36 @@ __device__ __forceinline__ int wave_sum(int v) {
 // floor(n / d) for small non-negative n, d (see div_small)
 __device__ __forceinline__ int qdiv(int n, double inv) { return (int)div_small((uint32_t)n, inv); }
 
-// Counts of one configuration from its pair sums (S x NP, then n_0..n_{M-2}, then the
-// bad-species flag), rows completed from the row-sum identity sum_j N_ij = z_k n_i,
-// then Eq. 2-3: R = N / (n_i n_j z_k), alpha = 1 - N_ij R, each row's (alpha - t)^2
-// summed over j, Q_k the sum of the rows, S = sum_k w_k Q_k, F = sqrt(S).  All
-// threads of the block call it; lc, lsq, lrow are LDS scratch.
+// Counts [M][M] of one shell from its sums pa (D_i at q(i,i), U_ij at q(i,j)),
+// the shell's coordination number and the species totals n: T entries from
+// D and U, then rows completed from sum_j N_ij = z_k n_i.
+template <int M>
+__device__ __forceinline__ void expand_shell(const int32_t *pa, int64_t zk, const int64_t *n, int32_t *c) {
+    constexpr int P = Pairs<M>::P;
+    for (int i = 0; i < P; ++i) {
+        const int32_t Di = pa[Pairs<M>::q(i, i)];
+        c[i * M + i] = 2 * Di;
+        for (int j = i + 1; j < P; ++j) {
+            const int32_t t = pa[Pairs<M>::q(i, j)] - Di - pa[Pairs<M>::q(j, j)];
+            c[i * M + j] = t;
+            c[j * M + i] = t;
+        }
+    }
+    int64_t last = 0;
+    for (int i = 0; i < P; ++i) {
+        int64_t r = zk * n[i];
+        for (int j = 0; j < P; ++j) r -= c[i * M + j];
+        c[i * M + (M - 1)] = (int32_t)r;
+        c[(M - 1) * M + i] = (int32_t)r;
+        last += r;
+    }
+    c[(M - 1) * M + (M - 1)] = (int32_t)(zk * n[M - 1] - last);
+}
+
+// Counts of one configuration from its sums (S x NP, then n_0..n_{M-2}, then the
+// bad-species flag), then Eq. 2-3: R = N / (n_i n_j z_k), alpha = 1 - N_ij R, each
+// row's (alpha - t)^2 summed over j, Q_k the sum of the rows, S = sum_k w_k Q_k,
+// F = sqrt(S).  All threads of the block call it; lc, lsq, lrow are LDS scratch.
 template <int M, int S>
 __device__ __forceinline__ void epilogue(const int32_t *pairs, const BitDesc &bd, int32_t *lc, double *lsq, double *lrow,
                          int32_t *cnt, int32_t *bad_out, const double *tw, double *S_F) {
@@ -87,26 +110,7 @@ __device__ __forceinline__ void epilogue(const int32_t *pairs, const BitDesc &bd
     const bool bad = pairs[S * NP + P] != 0;
     if (threadIdx.x < S) {
         const int k = threadIdx.x;
-        const int32_t *pa = pairs + k * NP;
-        int32_t *c = lc + k * M * M;
-        int q = 0;
-        for (int i = 0; i < P; ++i) {
-            c[i * M + i] = 2 * pa[q++];
-            for (int j = i + 1; j < P; ++j) {
-                c[i * M + j] = pa[q];
-                c[j * M + i] = pa[q];
-                ++q;
-            }
-        }
-        int64_t last = 0;
-        for (int i = 0; i < P; ++i) {
-            int64_t r = (int64_t)bd.zk[k] * n[i];
-            for (int j = 0; j < P; ++j) r -= c[i * M + j];
-            c[i * M + (M - 1)] = (int32_t)r;
-            c[(M - 1) * M + i] = (int32_t)r;
-            last += r;
-        }
-        c[(M - 1) * M + (M - 1)] = (int32_t)((int64_t)bd.zk[k] * n[M - 1] - last);
+        expand_shell<M>(pairs + k * NP, bd.zk[k], n, lc + k * M * M);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < S * M * M; e += blockDim.x) {
@@ -147,20 +151,40 @@ __device__ __forceinline__ void epilogue(const int32_t *pairs, const BitDesc &bd
     }
 }
 
+// P consecutive LDS dwords (16- or 8-byte loads where P allows: every group of
+// P dwords starts at a multiple of P dwords)
+template <int P>
+__device__ __forceinline__ void lds_planes(const uint32_t *p, uint32_t *v) {
+    if constexpr (P == 4) {
+        const uint4 t = *reinterpret_cast<const uint4 *>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+        v[2] = t.z;
+        v[3] = t.w;
+    } else if constexpr (P % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < P; i += 2) {
+            const uint2 t = *reinterpret_cast<const uint2 *>(p + i);
+            v[i] = t.x;
+            v[i + 1] = t.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < P; ++i) v[i] = p[i];
+    }
+}
+
 // MaxW: the wavefronts per SIMD the register allocation aims for -- 4 for a
 // workgroup alone on its CU (registers spent on overlapping loads), 8 when
 // several workgroups share the CU.
 template <int M, int S, int MaxW>
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4, MaxW)))
-count_bits_kernel(BitDesc bd, int64_t K,
-                                                               const int8_t *__restrict__ species,
-                                                               int32_t *__restrict__ partial,
-                                                               int32_t *__restrict__ counts_out,
-                                                               int32_t *__restrict__ bad_out,
-                                                               const double *__restrict__ tw,
-                                                               double *__restrict__ S_F) {
+count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int32_t *__restrict__ partial,
+                  int32_t *__restrict__ counts_out, int32_t *__restrict__ bad_out, const double *__restrict__ tw,
+                  double *__restrict__ S_F) {
     constexpr int P = Pairs<M>::P;
     constexpr int NP = Pairs<M>::NP;
+    constexpr int NV = S * NP + P;           // per-lane sums
     extern __shared__ __align__(16) uint32_t lds[];
     const int kc = blockIdx.y;
     if (kc >= K) return;
@@ -169,118 +193,116 @@ count_bits_kernel(BitDesc bd, int64_t K,
     const int nz = min(bd.ZC, bd.Lz - z0);   // centre layers of this workgroup
     const int nl = nz + 1;                   // plus the next layer (dz in {0, 1})
     const int PW = bd.PW;
-    const int LWD = 4 * P * PW;              // words per layer
-    uint32_t *cmask = lds + nl * LWD;        // centre mask per word [LW]
-    int32_t *red = (int32_t *)(cmask + bd.LW);  // reduction [S*NP + P + 1]
-    int32_t *tab = red + S * NP + P + 1;        // (delta, shift) per (basis, half offset)
+    const int RS = bd.RS;
+    const int nplane = nl * 4 * PW * P;      // plane dwords (a multiple of 4)
+    uint32_t *cmask = lds + nplane;          // centre mask per word [LW]
+    int32_t *red2 = (int32_t *)(cmask + bd.LW);  // per-lane sums [NV][64]
+    int32_t *red = red2 + NV * 64;               // totals [NV + 1]
+    int32_t *tab = red + NV + 1;                 // (delta, shift) per (basis, half offset)
     for (int i = threadIdx.x; i < 4 * bd.nh; i += blockDim.x) {
         tab[2 * i] = bd.tab_delta[i / bd.nh][i % bd.nh];
         tab[2 * i + 1] = bd.tab_r[i / bd.nh][i % bd.nh];
     }
 
-    // zero planes and the reduction area
-    const int nzero = nl * LWD;
-    for (int i = threadIdx.x; i < nzero; i += blockDim.x) lds[i] = 0;
-    for (int i = threadIdx.x; i < S * NP + P + 1; i += blockDim.x) red[i] = 0;
-    // centre mask: bit x of the flat array is a real site if row and column are inside
+    // zero planes and sums
+    {
+        uint4 *p4 = reinterpret_cast<uint4 *>(lds);
+        const uint4 z4 = {0u, 0u, 0u, 0u};
+        for (int i = threadIdx.x; i < nplane / 4; i += blockDim.x) p4[i] = z4;
+    }
+    for (int i = threadIdx.x; i < NV * 64 + NV + 1; i += blockDim.x) red2[i] = 0;
+    // centre mask: bit t of word w is a real site if its row and column are inside
     for (int w = threadIdx.x; w < bd.LW; w += blockDim.x) {
         const int x0 = 32 * w;
-        int row = x0 / bd.RS, col = x0 - row * bd.RS;
-        uint32_t m = 0;
-        for (int t = 0; t < 32; ++t) {
-            if (row >= 1 && row <= bd.Ly && col >= 1 && col <= bd.Lx) m |= 1u << t;
-            if (++col == bd.RS) {
-                col = 0;
-                ++row;
-            }
-        }
+        uint32_t m = 0xFFFFFFFFu;
+        const int lo = RS - x0;                  // bits below lo lie in row 0
+        if (lo > 0) m &= lo >= 32 ? 0u : (0xFFFFFFFFu << lo);
+        const int hi = (bd.Ly + 1) * RS - x0;    // bits from hi on lie in row Ly + 1 or beyond
+        if (hi < 32) m &= hi <= 0 ? 0u : (0xFFFFFFFFu >> (32 - hi));
+        const int c0 = x0 % RS;                  // column of bit 0
+        for (int t = (RS - c0) % RS; t < 32; t += RS) m &= ~(1u << t);               // column 0
+        for (int t = (2 * RS - 1 - c0) % RS; t < 32; t += RS) m &= ~(1u << t);       // column RS - 1
         cmask[w] = m;
     }
     __syncthreads();
 
-    // ---- 1. conversion ------------------------------------------------------------
-    const uint32_t *cfg = reinterpret_cast<const uint32_t *>(species + kc * (int64_t)bd.N);
+    // ---- 1. conversion: one padded row (layer ll, row fy) per item ------------------
+    const uint8_t *cfg = reinterpret_cast<const uint8_t *>(species) + kc * (int64_t)bd.N;
     uint32_t badacc = 0;
-    const int nitems = nl * bd.Ly * bd.nchx;
-    const double inv_nchx = 1.0 / bd.nchx, inv_rows = 1.0 / (bd.nchx * bd.Ly);
+    const uint32_t kBad = (0x80u - M) * 0x01010101u;   // byte + kBad has bit 7 set iff byte >= M (bytes < 0x80)
+    const int rows = bd.Ly + 2;
+    const int nitems = nl * rows;
+    const double inv_rows = 1.0 / rows;
 #pragma unroll 1
     for (int it = threadIdx.x; it < nitems; it += blockDim.x) {
         const int ll = qdiv(it, inv_rows);
-        const int rem = it - ll * bd.nchx * bd.Ly;
-        const int cy = qdiv(rem, inv_nchx);
-        const int cxc = rem - cy * bd.nchx;
+        const int fy = it - ll * rows;
+        int cy = fy - 1;
+        cy = cy < 0 ? bd.Ly - 1 : (cy >= bd.Ly ? 0 : cy);
         int cz = z0 + ll;
         if (cz >= bd.Lz) cz -= bd.Lz;
-        const int cx0 = 32 * cxc;
-        const int ncell = min(32, bd.Lx - cx0);
-        const uint32_t *row = cfg + ((int64_t)cz * bd.Ly + cy) * bd.Lx + cx0;
-        uint32_t acc[P][4];
-#pragma unroll
-        for (int j = 0; j < P; ++j)
-#pragma unroll
-            for (int g = 0; g < 4; ++g) acc[j][g] = 0;
-        const int ngroups = (ncell + 7) >> 3;
+        const uint32_t rowoff = (uint32_t)((cz * bd.Ly + cy) * bd.Lx) * 4u;
 #pragma unroll 1
-        for (int g = 0; g < ngroups; ++g) {
-            uint32_t part[P];
+        for (int cxc = 0; cxc < bd.nchx; ++cxc) {
+            uint32_t acc[P][4];
 #pragma unroll
-            for (int j = 0; j < P; ++j) part[j] = 0;
+            for (int g = 0; g < 4; ++g)
 #pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const int c = 8 * g + m;
-                const uint32_t d = row[min(c, ncell - 1)];
-                const uint32_t lane_pad = c < ncell ? 0u : 0xFFFFFFFFu;
-                // ids must be in [0, M): (d & 0x7f) + (0x80 - M) has its high bit set iff id >= M
-                badacc |= ((((d & 0x7F7F7F7Fu) + (0x80u - M) * 0x01010101u) | d) & ~lane_pad) & 0x80808080u;
+                for (int j = 0; j < P; ++j) acc[j][g] = 0;
+            // padded column pos holds cell (pos - 1) mod Lx; columns past the row
+            // end read cell 0 and are masked below, so every load is in bounds.
+            // GF groups of 8 loads are issued before any of them is used.
+            constexpr int GF = MaxW <= 4 ? 4 : 2;
 #pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    // one-hot lookup: byte value s -> (s == j)
-                    const uint64_t lut = 1ull << (8 * j);
-                    const uint32_t o = perm((uint32_t)(lut >> 32), (uint32_t)lut, d) & ~lane_pad;
-                    part[j] |= o << m;
+            for (int g0 = 0; g0 < 4; g0 += GF) {
+                uint32_t d[GF][8];
+#pragma unroll
+                for (int gg = 0; gg < GF; ++gg) {
+                    const int g = g0 + gg;
+                    if (32 * cxc + 8 * g >= RS) continue;   // uniform
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) {
+                        int c = 32 * cxc + 8 * g + m - 1;
+                        c = c < 0 ? bd.Lx - 1 : (c >= bd.Lx ? 0 : c);
+                        d[gg][m] = *reinterpret_cast<const uint32_t *>(cfg + (rowoff + 4u * (uint32_t)c));
+                    }
+                }
+#pragma unroll
+                for (int gg = 0; gg < GF; ++gg) {
+                    const int g = g0 + gg;
+                    if (32 * cxc + 8 * g >= RS) continue;
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) {
+                        badacc |= d[gg][m] | (d[gg][m] + kBad);
+#pragma unroll
+                        for (int j = 0; j < P; ++j) {
+                            // one-hot lookup: byte value s -> (s == j)
+                            const uint64_t lut = 1ull << (8 * j);
+                            acc[j][g] |= perm((uint32_t)(lut >> 32), (uint32_t)lut, d[gg][m]) << m;
+                        }
+                    }
                 }
             }
+            // 4x4 byte transpose: acc[j][g] byte b = bits of positions 8g..8g+7 of sublattice b
+            const int o = fy * RS + 32 * cxc;
+            const int wd = o >> 5, s = o & 31;
+            uint32_t *row0 = lds + (ll * 4 * PW + bd.PADW + wd) * P;
+            const int nvalid = RS - 32 * cxc;   // padded columns in this chunk
+            const uint32_t keep = nvalid >= 32 ? 0xFFFFFFFFu : (1u << nvalid) - 1u;
 #pragma unroll
             for (int j = 0; j < P; ++j) {
-                // groups are visited in order; select the slot without dynamic indexing
-                acc[j][0] = g == 0 ? part[j] : acc[j][0];
-                acc[j][1] = g == 1 ? part[j] : acc[j][1];
-                acc[j][2] = g == 2 ? part[j] : acc[j][2];
-                acc[j][3] = g == 3 ? part[j] : acc[j][3];
-            }
-        }
-        // 4x4 byte transpose: acc[j][g] byte b = bits of cells 8g..8g+7 of sublattice b
-        const bool last = cx0 + ncell == bd.Lx, first = cx0 == 0;
-        const int fr0 = cy + 1;
-        const int fr1 = cy == bd.Ly - 1 ? 0 : -1;       // periodic border rows
-        const int fr2 = cy == 0 ? bd.Ly + 1 : -1;
+                const uint32_t u0 = perm(acc[j][1], acc[j][0], 0x05010400u);
+                const uint32_t u1 = perm(acc[j][1], acc[j][0], 0x07030602u);
+                const uint32_t v0 = perm(acc[j][3], acc[j][2], 0x05010400u);
+                const uint32_t v1 = perm(acc[j][3], acc[j][2], 0x07030602u);
+                const uint32_t R[4] = {perm(v0, u0, 0x05040100u), perm(v0, u0, 0x07060302u),
+                                       perm(v1, u1, 0x05040100u), perm(v1, u1, 0x07060302u)};
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const uint32_t u0 = perm(acc[j][1], acc[j][0], 0x05010400u);
-            const uint32_t u1 = perm(acc[j][1], acc[j][0], 0x07030602u);
-            const uint32_t v0 = perm(acc[j][3], acc[j][2], 0x05010400u);
-            const uint32_t v1 = perm(acc[j][3], acc[j][2], 0x07030602u);
-            const uint32_t R[4] = {perm(v0, u0, 0x05040100u), perm(v0, u0, 0x07060302u),
-                                   perm(v1, u1, 0x05040100u), perm(v1, u1, 0x07060302u)};
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                uint32_t *plane = lds + ((ll * 4 + b) * P + j) * PW + bd.PADW;
-                const uint32_t r = R[b];
-                if (r == 0) continue;
-                const bool bl = last && ((r >> (ncell - 1)) & 1u);  // column 0 <- cell Lx-1
-                const bool bf = first && (r & 1u);                  // column Lx+1 <- cell 0
-                or_row(plane, fr0 * bd.RS + 1 + cx0, r);
-                if (bl) or_bit(plane, fr0 * bd.RS);
-                if (bf) or_bit(plane, fr0 * bd.RS + bd.Lx + 1);
-                if (fr1 >= 0) {
-                    or_row(plane, fr1 * bd.RS + 1 + cx0, r);
-                    if (bl) or_bit(plane, fr1 * bd.RS);
-                    if (bf) or_bit(plane, fr1 * bd.RS + bd.Lx + 1);
-                }
-                if (fr2 >= 0) {
-                    or_row(plane, fr2 * bd.RS + 1 + cx0, r);
-                    if (bl) or_bit(plane, fr2 * bd.RS);
-                    if (bf) or_bit(plane, fr2 * bd.RS + bd.Lx + 1);
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t r = R[b] & keep;
+                    uint32_t *dst = row0 + b * PW * P + j;
+                    atomicOr(dst, r << s);
+                    atomicOr(dst + P, (r >> 1) >> (31 - s));
                 }
             }
         }
@@ -293,9 +315,7 @@ count_bits_kernel(BitDesc bd, int64_t K,
     for (int k = 0; k < S; ++k)
 #pragma unroll
         for (int q = 0; q < NP; ++q) acc[k][q] = 0;
-    int32_t ncnt[P];
-#pragma unroll
-    for (int i = 0; i < P; ++i) ncnt[i] = 0;
+    const int lane = threadIdx.x & 63;
     const int nwork = nz * 4 * bd.NCW;
     const double inv_ncw = 1.0 / bd.NCW;
 #pragma unroll 1
@@ -305,61 +325,64 @@ count_bits_kernel(BitDesc bd, int64_t K,
         const int b = lb & 3;
         const int ll = lb >> 2;
         const uint32_t cm = cmask[w];
-        const uint32_t *pc = lds + (ll * 4 + b) * P * PW + bd.PADW + w;
+        const uint32_t *lbase = lds + (ll * 4 * PW + bd.PADW + w) * P;
         uint32_t Pv[P];
+        lds_planes<P>(lbase + b * PW * P, Pv);
 #pragma unroll
         for (int i = 0; i < P; ++i) {
-            Pv[i] = pc[i * PW] & cm;
-            ncnt[i] += __popc(Pv[i]);
+            Pv[i] &= cm;
+            // species totals go straight to this lane's slots (no registers held)
+            atomicAdd(&red2[(S * NP + i) * 64 + lane], (int32_t)__popc(Pv[i]));
         }
-        const uint32_t *lbase = lds + ll * LWD + bd.PADW + w;
+        uint32_t Un[NP];   // P_i | P_j at q(i, j), i < j
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+#pragma unroll
+            for (int j = i + 1; j < P; ++j) Un[Pairs<M>::q(i, j)] = Pv[i] | Pv[j];
+        const int32_t *tb = tab + 2 * b * bd.nh;
 #pragma unroll
         for (int k = 0; k < S; ++k) {
 #pragma unroll 1
             for (int h = bd.hstart[k]; h < bd.hstart[k + 1]; ++h) {
-                const int delta = tab[2 * (b * bd.nh + h)];
-                const uint32_t r = (uint32_t)tab[2 * (b * bd.nh + h) + 1];
-                const uint32_t *nb = lbase + delta;
-                uint32_t Q[P];
+                const uint32_t *nb = lbase + tb[2 * h];
+                const uint32_t r = (uint32_t)tb[2 * h + 1];
+                uint32_t lo[P], hi[P], Q[P];
+                lds_planes<P>(nb, lo);
+                lds_planes<P>(nb + P, hi);
 #pragma unroll
-                for (int j = 0; j < P; ++j) Q[j] = __builtin_amdgcn_alignbit(nb[j * PW + 1], nb[j * PW], r);
-                int q = 0;
+                for (int j = 0; j < P; ++j) Q[j] = __builtin_amdgcn_alignbit(hi[j], lo[j], r);
 #pragma unroll
                 for (int i = 0; i < P; ++i) {
-                    acc[k][q] += __popc(Pv[i] & Q[i]);
-                    ++q;
+                    acc[k][Pairs<M>::q(i, i)] += __popc(Pv[i] & Q[i]);
 #pragma unroll
-                    for (int j = i + 1; j < P; ++j) {
-                        // (P_i & Q_j) | (P_j & Q_i): one AND and one three-input op (0xEA = (a & b) | c)
-                        acc[k][q] += __popc(__builtin_amdgcn_bitop3_b32(Pv[i], Q[j], Pv[j] & Q[i], 0xEA));
-                        ++q;
-                    }
+                    for (int j = i + 1; j < P; ++j)
+                        // (P_i | P_j) & (Q_i | Q_j): one three-input op (0xE0 = a & (b | c))
+                        acc[k][Pairs<M>::q(i, j)] +=
+                            __popc(__builtin_amdgcn_bitop3_b32(Un[Pairs<M>::q(i, j)], Q[i], Q[j], 0xE0));
                 }
             }
         }
     }
-    // ---- 3. reduce over the workgroup, then into the per-configuration partials ------
-#pragma unroll
-    for (int k = 0; k < S; ++k)
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-            const int v = wave_sum(acc[k][q]);
-            if ((threadIdx.x & 63) == 63 && v) atomicAdd(&red[k * NP + q], v);
-        }
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const int v = wave_sum(ncnt[i]);
-        if ((threadIdx.x & 63) == 63 && v) atomicAdd(&red[S * NP + i], v);
-    }
+    // ---- 3. reduce over the workgroup: per-lane slots, then one wave_sum per value ----
     {
-        uint64_t anybad = __ballot(badacc != 0);
-        if ((threadIdx.x & 63) == 0 && anybad) atomicOr(&red[S * NP + P], 1);
+#pragma unroll
+        for (int k = 0; k < S; ++k)
+#pragma unroll
+            for (int q = 0; q < NP; ++q) atomicAdd(&red2[(k * NP + q) * 64 + lane], acc[k][q]);
+        const uint64_t anybad = __ballot((badacc & 0x80808080u) != 0);
+        if (lane == 0 && anybad) atomicOr(&red[NV], 1);
+        __syncthreads();
+        const int nwaves = blockDim.x >> 6;
+        for (int v = threadIdx.x >> 6; v < NV; v += nwaves) {
+            const int t = wave_sum(red2[v * 64 + lane]);
+            if (lane == 63) red[v] = t;
+        }
     }
     __syncthreads();
     if (bd.nchunks > 1) {
         int32_t *out = partial + kc * (int64_t)bd.partial_stride;
-        for (int i = threadIdx.x; i < S * NP + P + 1; i += blockDim.x) {
-            if (i < S * NP + P)
+        for (int i = threadIdx.x; i < NV + 1; i += blockDim.x) {
+            if (i < NV)
                 atomicAdd(&out[i], red[i]);
             else if (red[i])
                 atomicOr(&out[i], red[i]);
@@ -393,28 +416,7 @@ __global__ void finalize_bits_kernel(BitDesc bd, int64_t K, const int32_t *__res
     }
     n[M - 1] = rest;
     bad[kc] = pa[S * NP + P] ? 1 : 0;
-    for (int k = 0; k < S; ++k) {
-        int q = 0;
-        for (int i = 0; i < P; ++i) {
-            c[(k * M + i) * M + i] = 2 * pa[k * NP + q];
-            ++q;
-            for (int j = i + 1; j < P; ++j) {
-                c[(k * M + i) * M + j] = pa[k * NP + q];
-                c[(k * M + j) * M + i] = pa[k * NP + q];
-                ++q;
-            }
-        }
-        // rows sum to z_k n_i
-        int64_t last_col_sum = 0;
-        for (int i = 0; i < P; ++i) {
-            int64_t r = (int64_t)bd.zk[k] * n[i];
-            for (int j = 0; j < P; ++j) r -= c[(k * M + i) * M + j];
-            c[(k * M + i) * M + (M - 1)] = (int32_t)r;
-            c[(k * M + (M - 1)) * M + i] = (int32_t)r;
-            last_col_sum += r;
-        }
-        c[(k * M + (M - 1)) * M + (M - 1)] = (int32_t)((int64_t)bd.zk[k] * n[M - 1] - last_col_sum);
-    }
+    for (int k = 0; k < S; ++k) expand_shell<M>(pa + k * NP, bd.zk[k], n, c + k * M * M);
 }
 
 // partial sums -> counts and Eq. 2-3 (one 64-thread block per configuration)
@@ -441,7 +443,8 @@ template <int M, int S>
 hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_t *partial, int32_t *counts,
                      int32_t *bad, const double *tw, double *S_F, hipStream_t stream) {
     const int P = M - 1;
-    const size_t lds = ((size_t)(bd.ZC + 1) * 4 * P * bd.PW + bd.LW + S * Pairs<M>::NP + P + 1 + 8 * bd.nh + 1 +
+    const int NV = S * Pairs<M>::NP + P;
+    const size_t lds = ((size_t)(bd.ZC + 1) * 4 * P * bd.PW + bd.LW + NV * 64 + NV + 1 + 8 * bd.nh + 1 +
                         3 * S * M * M + 2 * S * M + 2) * 4;
     const bool lone = bd.threads > 512;   // one workgroup per CU
     const void *fn = lone ? (const void *)count_bits_kernel<M, S, 4> : (const void *)count_bits_kernel<M, S, 8>;
@@ -501,7 +504,7 @@ LaunchFn pick(int M, int S) {
 
 }  // namespace
 
-bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, BitDesc *bd) {
+bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitDesc *bd) {
     std::memset(bd, 0, sizeof(*bd));
     if (g.lattice != PYHEA_FCC || g.halo != 1 || !pick(g.M, g.S)) return false;
     const int P = g.M - 1;
@@ -515,15 +518,20 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, BitDesc *bd) {
     bd->PW = bd->LW + 2 * bd->PADW;
     bd->cw0 = bd->RS / 32;
     bd->NCW = ((g.L[1] + 1) * bd->RS - 1) / 32 - bd->cw0 + 1;
-    bd->nchx = (g.L[0] + 31) / 32;
+    bd->nchx = (bd->RS + 31) / 32;
     bd->N = (uint32_t)g.N;
     const int np = P * (P + 1) / 2;
     bd->partial_stride = ((g.S * np + P + 1) + 3) & ~3;
     for (int k = 0; k < kMaxShells; ++k) bd->zk[k] = k < g.S ? g.z[k] : 0;
     // largest z-chunk whose planes fit in LDS
-    const int fixed = (bd->LW + g.S * np + P + 1 + 8 * kMaxOffsets / 2 + 3 * g.S * g.M * g.M + 2 * g.S * g.M + 3) * 4;
+    const int nv = g.S * np + P;
+    const int fixed = (bd->LW + nv * 64 + nv + 1 + 8 * kMaxOffsets / 2 + 3 * g.S * g.M * g.M + 2 * g.S * g.M + 3) * 4;
     const int per_layer = 4 * P * bd->PW * 4;
-    int zc = (lds_budget - fixed) / per_layer - 1;
+    // split > 1: a configuration whose layers would take more than 1/split of a
+    // CU's LDS is cut along z so that `split` workgroups share each CU
+    const int budget = split > 1 && fixed + (g.L[2] + 1) * per_layer > lds_budget / split ? lds_budget / split
+                                                                                          : lds_budget;
+    int zc = (budget - fixed) / per_layer - 1;
     if (zc < 1) return false;
     zc = std::min(zc, g.L[2]);
     zc = (g.L[2] + (g.L[2] + zc - 1) / zc - 1) / ((g.L[2] + zc - 1) / zc);
@@ -550,7 +558,7 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, BitDesc *bd) {
                 const int s = dc[1] * bd->RS + dc[0];
                 const int q = s >= 0 ? s / 32 : -((-s + 31) / 32);
                 const int r = s - 32 * q;
-                bd->tab_delta[b][nh] = (dc[2] * 4 + bt) * P * bd->PW + q;
+                bd->tab_delta[b][nh] = ((dc[2] * 4 + bt) * bd->PW + q) * P;
                 bd->tab_r[b][nh] = r;
             }
             ++nh;

@@ -91,7 +91,7 @@ BATCH_SHAPES = [
 ]
 
 
-@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3])
 @pytest.mark.parametrize("lattice,L,M,S,K", BATCH_SHAPES)
 def test_sro_eval_batch_matches_oracle(lattice, L, M, S, K, kernel):
     pb.pyhea_tune_force_eval(kernel)
