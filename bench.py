@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (one after another) chains")
     ap.add_argument("--serve-jobs", type=int, default=2000, help="served jobs (0 = skip serving)")
     ap.add_argument("--serve-budget-mb", type=int, default=512)
+    ap.add_argument("--no-global", action="store_true", help="skip the global search leg")
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered load / batched capacity")
     return ap.parse_args()
 
@@ -156,6 +157,26 @@ def serve(pb, wl, n_jobs, capacity_trials_per_s, load, budget_mb):
             "latency_ms_max": float(lat.max()), "admission_wait_ms_p50": float(np.percentile(wait, 50)),
             "admission_wait_ms_p99": float(np.percentile(wait, 99)), "trials": int(trials), "span_s": span,
             "trials_per_s": trials / span, "rounds": c["rounds"], "sites_total": int(sum(j.N for j in jobs))}
+
+
+def global_search(pb, p, torch):
+    """Algorithm 1 with the paper's Performance-Optimized preset (64 solutions,
+    6 global iterations, 64 tasks, search depth 8) on the FCC 20^3 problem: the
+    32 best solutions of each iteration refined (at most 10^5 trial swaps each),
+    half of them kept as seeds.  One warm-up search, then one timed search."""
+    comp = np.bincount(p.species, minlength=p.M)
+    best = torch.empty(p.N, dtype=torch.int8, device="cuda")
+    kw = dict(n_solutions=64, iterations=6, n_refine=32, discard_frac=0.5, seed=p.seed, B=64,
+              n_trials=10**5, depth_limit=8)
+    pb.pyhea_global_search(p.lattice, p.L, p.M, p.S, p.target, p.weight, comp, best, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, hist = pb.pyhea_global_search(p.lattice, p.L, p.M, p.S, p.target, p.weight, comp, best, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"s": dt, "evaluations": st["evaluations"], "trials": st["trials"], "commits": st["commits"],
+            "trials_per_s": st["trials"] / dt, "best_F": st["F"], "best_F_per_iteration": [float(x) for x in hist],
+            "preset": "64 solutions, 6 iterations, 32 refined (<= 1e5 trials, depth 8, B = 64), p_a = 0.5"}
 
 
 def main():
@@ -345,6 +366,8 @@ def main():
     if args.serve_jobs > 0:
         cap = out.get("batched", {}).get("trials_per_s", 1.0e9)
         out["serving"] = serve(pb, wl, args.serve_jobs, cap, args.serve_load, args.serve_budget_mb)
+    if not args.no_global:
+        out["global_search"] = global_search(pb, p, torch)
     if "value" not in out:
         out["value"] = None
     if not args.no_cpu_baseline:

@@ -102,6 +102,34 @@ typedef struct {
     int64_t log_len;     /* accepted-swap records written (min(commits, cap))  */
 } pyhea_mc_stats;
 
+/* Global search parameters (Sec. 5.1, Algorithm 1; the parameter study of
+ * Sec. 2.3 names the pool size, the global iterations, the tasks and the
+ * search depth). */
+typedef struct {
+    int32_t n_solutions;   /* solutions in the pool, >= 1                          */
+    int32_t iterations;    /* global iterations, >= 1                               */
+    int32_t n_refine;      /* best solutions refined per iteration, 1..n_solutions  */
+    int32_t pad;
+    double discard_frac;   /* p_a in [0, 1]: share of the refined solutions dropped;
+                              the best n_refine - ceil(p_a n_refine), at most
+                              n_refine / 2, seed the next iteration                  */
+    pyhea_mc_params local; /* local search of every refined solution: seed (also
+                              keys the random solutions), cand_per_step ("tasks"),
+                              n_trials (cap per refinement), commit_mode,
+                              depth_limit ("search depth"), accept_tol; chain_id is
+                              ignored (each refinement uses iteration *
+                              n_solutions + pool slot)                              */
+} pyhea_global_params;
+
+/* Global search results. */
+typedef struct {
+    int64_t evaluations; /* full evaluations of pool solutions                   */
+    int64_t trials;      /* trial swaps of all local searches                     */
+    int64_t commits;     /* swaps applied by all local searches                   */
+    double S;            /* objective of the best solution                        */
+    double F;            /* sqrt(S) of the best solution                          */
+} pyhea_global_stats;
+
 /* Library version (major * 10000 + minor * 100 + patch). */
 int32_t pyhea_version(void);
 
@@ -224,6 +252,41 @@ pyhea_status pyhea_serve_counters(void *server, int64_t *out8_host);
 
 /* Stop the worker, drop unfinished jobs and free the server. */
 pyhea_status pyhea_serve_close(void *server);
+
+/*
+ * Global search (Sec. 5.1, Algorithm 1).  Iteration t: solutions without a
+ * retained seed are drawn at random (pyhea_random_configs with iteration t);
+ * every pool solution is evaluated in full (Eq. 3); the n_refine best (by F,
+ * then pool slot) are refined by the Monte Carlo local search of
+ * pyhea_mc_batch; the refined ones are ranked by their final F (then by their
+ * rank before refinement), the worst fraction p_a is dropped and the best
+ * retained ones move to pool slots 0.. as the next iteration's seeds; the best
+ * solution so far is replaced only by a strictly lower F.
+ *   composition_host  [M] species counts, host; each >= 1, summing to N.
+ *   best_dev          [N] int8, device: the best solution found.
+ *   history_host      [iterations] best F after each iteration, host, or NULL.
+ *   stats_host        results, host.
+ * Device memory for the pool is allocated per call.  Synchronous.
+ */
+pyhea_status pyhea_global_search(const pyhea_lattice *lat, const pyhea_objective *obj,
+                                 const int64_t *composition_host, const pyhea_global_params *params,
+                                 int8_t *best_dev, double *history_host, pyhea_global_stats *stats_host,
+                                 void *stream);
+
+/*
+ * Random solutions of the global search (Sec. 5.1: new candidate
+ * configurations; the paper does not say how they are drawn).  Configuration
+ * c (0 <= c < n_configs) is pool slot slot0 + c of iteration `iteration`: the
+ * species list sorted by species (composition_host[j] copies of j) placed on
+ * the sites through a keyed permutation -- a four-round Feistel network on
+ * 2h-bit values (4^h >= N), round r XOR-ing the low h bits of word 0 of
+ * Philox4x32-10(counter = (right half, r, slot, 0x80000000 | iteration), key =
+ * seed) into the left half, re-applied until the value is below N.
+ *   out_dev  [n_configs][N] int8, device.  Asynchronous.
+ */
+pyhea_status pyhea_random_configs(int64_t N, int32_t M, const int64_t *composition_host, uint64_t seed,
+                                  uint32_t iteration, uint32_t slot0, int32_t n_configs, int8_t *out_dev,
+                                  void *stream);
 
 /* Philox4x32-10 (Salmon et al., SC'11) on the device, for checking the
  * library's trial draws: out[i] = philox(ctr[i], key = (lo32(seed), hi32(seed))).

@@ -81,6 +81,8 @@ def lib():
                                 i32, i32, i32, ctypes.c_double, P, P, i64,
                                 ctypes.POINTER(McStats), P]
         L.or_mc_run.restype = i32
+        L.or_random_config.argtypes = [i64, i32, P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, P]
+        L.or_random_config.restype = i32
         _lib = L
     return _lib
 
@@ -189,3 +191,76 @@ def mc_run(lattice: int, L, M: int, S: int, target, weight, species: np.ndarray,
     if rc != 0:
         raise ValueError(f"oracle rejected the problem (code {rc})")
     return sp, log[: st.log_len].copy(), st.as_dict(), cnt
+
+
+def random_config(N: int, composition, *, seed: int, iteration: int, slot: int) -> np.ndarray:
+    """A new solution of the global search: the composition-sorted species list
+    placed through a keyed Feistel permutation of the sites (sro_oracle.c)."""
+    comp = np.ascontiguousarray(np.asarray(composition, dtype=np.int64))
+    out = np.full(N, -1, np.int8)
+    rc = lib().or_random_config(N, comp.size, _p(comp), seed, iteration, slot, _p(out))
+    if rc != 0:
+        raise ValueError("composition does not add up to N")
+    return out
+
+
+def retained_count(n_refine: int, discard_frac: float) -> int:
+    """Solutions kept as seeds after an iteration: the refined ones minus the
+    discarded fraction p_a (rounded up), at most half of those refined."""
+    return max(0, min(n_refine // 2, n_refine - int(np.ceil(discard_frac * n_refine))))
+
+
+def global_search(lattice: int, L, M: int, S: int, target, weight, composition, *,
+                  n_solutions: int, iterations: int, n_refine: int, discard_frac: float,
+                  seed: int, B: int, n_trials: int, mode: int = MODE_DISJOINT,
+                  depth_limit: int = 0, tau: float = 0.0, trace: list | None = None):
+    """Algorithm 1 (Sec. 5.1), in its order:
+      pool: iteration 0 draws every solution at random; later iterations keep
+        the seeds retained by the previous one in slots 0..R-1 and draw new
+        random solutions into the rest;
+      fitness F (Eq. 3) of every solution from a full evaluation;
+      the n_refine best (by F, then slot) are refined by Monte Carlo local
+        search (mc_run, chain id = iteration * n_solutions + slot);
+      refined solutions ranked by final F (then by their rank before the
+        refinement); the worst fraction p_a is discarded and the best R =
+        retained_count(...) become the next iteration's seeds;
+      the best solution so far is kept (a later one replaces it only if its F
+        is strictly lower).
+    Returns (best species, best S, best F, best F after each iteration, stats)."""
+    N = n_sites(lattice, L)
+    if not (1 <= n_refine <= n_solutions) or iterations < 1 or not (0.0 <= discard_frac <= 1.0):
+        raise ValueError("bad global search parameters")
+    R = retained_count(n_refine, discard_frac)
+    pool = [None] * n_solutions
+    kept = 0
+    best_F, best_S, best = np.inf, np.inf, None
+    history = []
+    st = {"trials": 0, "commits": 0, "evaluations": 0}
+    for t in range(iterations):
+        for s in range(kept, n_solutions):
+            pool[s] = random_config(N, composition, seed=seed, iteration=t, slot=s)
+        F = []
+        for s in range(n_solutions):
+            _, _, _, f = alpha_objective(lattice, L, M, S, pool[s], counts(lattice, L, M, S, pool[s]),
+                                         target, weight)
+            F.append(f)
+        st["evaluations"] += n_solutions
+        top = sorted(range(n_solutions), key=lambda s: (F[s], s))[:n_refine]
+        refined = []
+        for rank, s in enumerate(top):
+            sp, _, ms, _ = mc_run(lattice, L, M, S, target, weight, pool[s], seed=seed,
+                                  chain_id=t * n_solutions + s, n_trials=n_trials, B=B, mode=mode,
+                                  depth_limit=depth_limit, tau=tau, log_cap=0)
+            st["trials"] += ms["trials"]
+            st["commits"] += ms["commits"]
+            refined.append((ms["F"], rank, ms["S"], sp))
+        refined.sort(key=lambda r: (r[0], r[1]))
+        if refined[0][0] < best_F:
+            best_F, best_S, best = refined[0][0], refined[0][2], refined[0][3].copy()
+        history.append(best_F)
+        if trace is not None:
+            trace.append({"F": F, "top": top, "refined_F": [r[0] for r in refined]})
+        for s in range(R):
+            pool[s] = refined[s][3]
+        kept = R
+    return best, best_S, best_F, np.array(history), st

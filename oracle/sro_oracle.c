@@ -574,3 +574,54 @@ int or_mc_run(int lattice, const int *L, int M, int S, const double *target,
     free(committed);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* New solutions of the global search (Sec. 5.1, Algorithm 1): a random      */
+/* arrangement of a fixed composition.  The paper does not say how a random  */
+/* configuration is drawn; here position i of the composition-sorted list    */
+/* (species j for c_0 + ... + c_{j-1} <= i < c_0 + ... + c_j) is placed on   */
+/* site pi(i), pi a keyed permutation of [0, N):                             */
+/*   * a balanced Feistel network on 2h-bit values (h the smallest h >= 1    */
+/*     with 4^h >= N), four rounds; round r maps (L, R) to (R, L ^ f) with    */
+/*     f = low h bits of word 0 of Philox4x32-10(counter = (R, r, slot,      */
+/*     0x80000000 | iteration), key = seed);                                 */
+/*   * cycle walking: the network is applied again until the value is < N   */
+/*     (it is a permutation of [0, 4^h), so the orbit of i < N returns below */
+/*     N, and the map restricted to [0, N) is a permutation).                */
+/* ------------------------------------------------------------------------ */
+
+static uint32_t feistel4(uint32_t x, int h, uint32_t slot, uint32_t iteration, const uint32_t *key) {
+    const uint32_t mask = (1u << h) - 1u;
+    uint32_t l = x >> h, r = x & mask;
+    for (uint32_t round = 0; round < 4; ++round) {
+        const uint32_t ctr[4] = {r, round, slot, 0x80000000u | iteration};
+        uint32_t out[4];
+        or_philox4x32_10(ctr, key, out);
+        const uint32_t nl = r;
+        r = l ^ (out[0] & mask);
+        l = nl;
+    }
+    return (l << h) | r;
+}
+
+int or_random_config(int64_t N, int M, const int64_t *composition, uint64_t seed, uint32_t iteration,
+                     uint32_t slot, int8_t *out) {
+    int64_t total = 0;
+    for (int j = 0; j < M; ++j) {
+        if (composition[j] < 0) return 1;
+        total += composition[j];
+    }
+    if (total != N || N < 1 || N > (int64_t)1 << 30) return 1;
+    int h = 1;
+    while (((int64_t)1 << (2 * h)) < N) ++h;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    int j = 0;
+    int64_t end = composition[0];
+    for (int64_t i = 0; i < N; ++i) {
+        while (i >= end) end += composition[++j];
+        uint32_t x = feistel4((uint32_t)i, h, slot, iteration, key);
+        while (x >= (uint64_t)N) x = feistel4(x, h, slot, iteration, key);
+        out[x] = (int8_t)j;
+    }
+    return 0;
+}

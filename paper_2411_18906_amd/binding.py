@@ -26,7 +26,8 @@ EXPORTS = [
     "pyhea_trial_eval", "pyhea_mc_run", "pyhea_mc_batch", "pyhea_serve_open",
     "pyhea_serve_submit", "pyhea_serve_poll", "pyhea_serve_cancel", "pyhea_serve_counters",
     "pyhea_serve_close", "pyhea_philox4x32_10", "pyhea_tune_force",
-    "pyhea_tune_force_eval", "pyhea_tune_force_lookahead",
+    "pyhea_tune_force_eval", "pyhea_tune_force_lookahead", "pyhea_global_search",
+    "pyhea_random_configs",
 ]
 
 
@@ -50,6 +51,20 @@ class McParams(ctypes.Structure):
                 ("cand_per_step", ctypes.c_int32), ("n_trials", ctypes.c_int64),
                 ("commit_mode", ctypes.c_int32), ("depth_limit", ctypes.c_int32),
                 ("accept_tol", ctypes.c_double)]
+
+
+class GlobalParams(ctypes.Structure):
+    _fields_ = [("n_solutions", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("n_refine", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("discard_frac", ctypes.c_double), ("local", McParams)]
+
+
+class GlobalStats(ctypes.Structure):
+    _fields_ = [("evaluations", ctypes.c_int64), ("trials", ctypes.c_int64),
+                ("commits", ctypes.c_int64), ("S", ctypes.c_double), ("F", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class McStats(ctypes.Structure):
@@ -91,6 +106,8 @@ def lib():
             "pyhea_tune_force": ([i32], i32),
             "pyhea_tune_force_eval": ([i32], i32),
             "pyhea_tune_force_lookahead": ([i32], i32),
+            "pyhea_global_search": ([P, P, P, P, P, P, P, P], i32),
+            "pyhea_random_configs": ([i64, i32, P, u64, ctypes.c_uint32, ctypes.c_uint32, i32, P, P], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -236,6 +253,33 @@ def pyhea_philox4x32_10(ctr, seed: int, out, stream=None):
     import torch
     _check(lib().pyhea_philox4x32_10(_dptr(ctr, torch.int32), seed, ctr.shape[0],
                                      _dptr(out, torch.int32), _stream(stream)))
+
+
+def pyhea_random_configs(N: int, composition, seed: int, iteration: int, slot0: int, out, stream=None):
+    """Random global-search solutions into out[n][N] (device int8)."""
+    import torch
+    comp = np.ascontiguousarray(np.asarray(composition, dtype=np.int64))
+    _check(lib().pyhea_random_configs(N, comp.size, _hptr(comp), seed, iteration, slot0, out.shape[0],
+                                      _dptr(out, torch.int8), _stream(stream)))
+
+
+def pyhea_global_search(lattice: int, L, M: int, S: int, target, weight, composition, best, *,
+                        n_solutions: int, iterations: int, n_refine: int, discard_frac: float,
+                        seed: int, B: int, n_trials: int, mode: int = MODE_DISJOINT,
+                        depth_limit: int = 0, tau: float = 0.0, stream=None):
+    """Algorithm 1; best (device int8 [N]) receives the best solution.
+    Returns (stats dict, best F after each iteration)."""
+    import torch
+    lat = make_lattice(lattice, L, M, S)
+    obj = _Obj(target, weight, S, M)
+    comp = np.ascontiguousarray(np.asarray(composition, dtype=np.int64))
+    p = GlobalParams(n_solutions, iterations, n_refine, 0, discard_frac,
+                     make_params(seed, 0, n_trials, B, mode, depth_limit, tau))
+    hist = np.zeros(max(iterations, 1))
+    st = GlobalStats()
+    _check(lib().pyhea_global_search(ctypes.byref(lat), ctypes.byref(obj.c), _hptr(comp), ctypes.byref(p),
+                                     _dptr(best, torch.int8), _hptr(hist), ctypes.byref(st), _stream(stream)))
+    return st.as_dict(), hist[:iterations]
 
 
 def pyhea_tune_force(variant: int):

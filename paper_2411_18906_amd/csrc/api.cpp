@@ -2,8 +2,11 @@
 // entry point).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -260,6 +263,149 @@ pyhea_status pyhea_mc_batch(int32_t n_chains, const pyhea_lattice *lats, const p
     }
     pyhea_status s = run_chains(jobs, stats_host, nullptr, as_stream(stream), forced_variant());
     return s == PYHEA_OK ? guard(s) : s;
+}
+
+static pyhea_status random_desc(int64_t N, int32_t M, const int64_t *comp, uint64_t seed, uint32_t iteration,
+                                uint32_t slot0, RandomConfigDesc *d) {
+    if (N < 1 || N > (int64_t(1) << 30) || M < 1 || M > 8 || !comp) {
+        set_error("N must be in [1, 2^30], M in [1, 8], composition non-NULL");
+        return PYHEA_EINVAL;
+    }
+    std::memset(d, 0, sizeof(*d));
+    d->seed = seed;
+    d->iteration = iteration;
+    d->slot0 = slot0;
+    d->M = M;
+    int64_t total = 0;
+    for (int j = 0; j < M; ++j) {
+        if (comp[j] < 0) {
+            set_error("species counts must be >= 0");
+            return PYHEA_EINVAL;
+        }
+        d->prefix[j] = (uint32_t)total;
+        total += comp[j];
+        if (total > N) break;
+    }
+    if (total != N) {
+        set_error("species counts must add up to N");
+        return PYHEA_EINVAL;
+    }
+    d->prefix[M] = (uint32_t)N;
+    return PYHEA_OK;
+}
+
+pyhea_status pyhea_random_configs(int64_t N, int32_t M, const int64_t *composition_host, uint64_t seed,
+                                  uint32_t iteration, uint32_t slot0, int32_t n_configs, int8_t *out_dev,
+                                  void *stream) {
+    RandomConfigDesc d;
+    pyhea_status s = random_desc(N, M, composition_host, seed, iteration, slot0, &d);
+    if (s != PYHEA_OK) return s;
+    if (n_configs < 0 || (n_configs > 0 && !out_dev)) {
+        set_error("n_configs must be >= 0 and out_dev non-NULL");
+        return PYHEA_EINVAL;
+    }
+    PYHEA_HIP(launch_random_configs((uint32_t)N, d, n_configs, out_dev, as_stream(stream)));
+    return guard(PYHEA_OK);
+}
+
+pyhea_status pyhea_global_search(const pyhea_lattice *lat, const pyhea_objective *obj,
+                                 const int64_t *composition_host, const pyhea_global_params *params,
+                                 int8_t *best_dev, double *history_host, pyhea_global_stats *stats_host,
+                                 void *stream_) {
+    if (!params || !best_dev || !stats_host || !obj) {
+        set_error("params, obj, best_dev and stats_host must not be NULL");
+        return PYHEA_EINVAL;
+    }
+    const pyhea_global_params &P = *params;
+    if (P.n_solutions < 1 || P.iterations < 1 || P.n_refine < 1 || P.n_refine > P.n_solutions ||
+        !(P.discard_frac >= 0.0 && P.discard_frac <= 1.0)) {
+        set_error("need n_solutions >= 1, iterations >= 1, 1 <= n_refine <= n_solutions, 0 <= p_a <= 1");
+        return PYHEA_EINVAL;
+    }
+    ChainJob proto;
+    pyhea_status s = make_job(lat, obj, &P.local, &proto, "");
+    if (s != PYHEA_OK) return s;
+    const Geometry &g = proto.g;
+    const int64_t N = g.N;
+    if ((int64_t)P.n_solutions * P.iterations > (int64_t)UINT32_MAX) {
+        set_error("n_solutions * iterations must fit the 32-bit chain id");
+        return PYHEA_EINVAL;
+    }
+    RandomConfigDesc rd;
+    s = random_desc(N, g.M, composition_host, P.local.seed, 0, 0, &rd);
+    if (s != PYHEA_OK) return s;
+    for (int j = 0; j < g.M; ++j)
+        if (composition_host[j] < 1) {
+            set_error("every species needs at least one site (Eq. 2 divides by its count)");
+            return PYHEA_EINVAL;
+        }
+    const int n = P.n_solutions, T = P.n_refine;
+    const int R = std::max(0, std::min(T / 2, T - (int)std::ceil(P.discard_frac * T)));
+    hipStream_t stream = as_stream(stream_);
+    const int E = g.S * g.M * g.M;
+    // pool [n][N] | refine [T][N] | counts [n][E] int32 | S_F [n][2]
+    const size_t o_ref = ((size_t)n * N + 255) & ~size_t(255);
+    const size_t o_cnt = (o_ref + (size_t)T * N + 255) & ~size_t(255);
+    const size_t o_sf = (o_cnt + (size_t)n * E * 4 + 255) & ~size_t(255);
+    AsyncBuffer buf;
+    buf.stream = stream;
+    PYHEA_HIP(pool_alloc(&buf.ptr, o_sf + (size_t)n * 16, stream));
+    int8_t *pool = (int8_t *)buf.ptr;
+    int8_t *refine = pool + o_ref;
+    int32_t *counts = (int32_t *)((char *)buf.ptr + o_cnt);
+    double *SF = (double *)((char *)buf.ptr + o_sf);
+    std::vector<double> sf(2 * (size_t)n);
+    std::vector<pyhea_mc_stats> ms(T);
+    pyhea_global_stats st{};
+    st.S = st.F = std::numeric_limits<double>::infinity();
+    int kept = 0;
+    for (int t = 0; t < P.iterations; ++t) {
+        // new random solutions in the slots without a seed
+        rd.iteration = (uint32_t)t;
+        rd.slot0 = (uint32_t)kept;
+        PYHEA_HIP(launch_random_configs((uint32_t)N, rd, n - kept, pool + (int64_t)kept * N, stream));
+        // fitness of every solution (Eq. 3)
+        s = pyhea_sro_eval_batch(lat, n, pool, obj, counts, SF, stream);
+        if (s != PYHEA_OK) return s;
+        PYHEA_HIP(hipMemcpyAsync(sf.data(), SF, sf.size() * 8, hipMemcpyDeviceToHost, stream));
+        PYHEA_HIP(hipStreamSynchronize(stream));
+        st.evaluations += n;
+        std::vector<int> order(n);
+        for (int i = 0; i < n; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return sf[2 * a + 1] < sf[2 * b + 1]; });
+        // local search of the n_refine best, in rank order
+        std::vector<ChainJob> jobs(T, proto);
+        for (int r = 0; r < T; ++r) {
+            PYHEA_HIP(hipMemcpyAsync(refine + (int64_t)r * N, pool + (int64_t)order[r] * N, N,
+                                     hipMemcpyDeviceToDevice, stream));
+            jobs[r].species_dev = refine + (int64_t)r * N;
+            jobs[r].params.chain_id = (uint32_t)(t * n + order[r]);
+        }
+        s = run_chains(jobs, ms.data(), nullptr, stream, forced_variant());
+        if (s != PYHEA_OK) return s;
+        std::vector<int> rank(T);
+        for (int r = 0; r < T; ++r) {
+            rank[r] = r;
+            st.trials += ms[r].trials;
+            st.commits += ms[r].commits;
+        }
+        std::stable_sort(rank.begin(), rank.end(), [&](int a, int b) { return ms[a].F < ms[b].F; });
+        if (ms[rank[0]].F < st.F) {
+            st.F = ms[rank[0]].F;
+            st.S = ms[rank[0]].S;
+            PYHEA_HIP(hipMemcpyAsync(best_dev, refine + (int64_t)rank[0] * N, N, hipMemcpyDeviceToDevice, stream));
+        }
+        if (history_host) history_host[t] = st.F;
+        // the best R refined solutions seed the next iteration
+        for (int i = 0; i < R; ++i)
+            PYHEA_HIP(hipMemcpyAsync(pool + (int64_t)i * N, refine + (int64_t)rank[i] * N, N,
+                                     hipMemcpyDeviceToDevice, stream));
+        kept = R;
+    }
+    PYHEA_HIP(hipStreamSynchronize(stream));
+    *stats_host = st;
+    return guard(PYHEA_OK);
 }
 
 pyhea_status pyhea_philox4x32_10(const uint32_t *ctr_dev, uint64_t seed, int64_t n, uint32_t *out_dev,

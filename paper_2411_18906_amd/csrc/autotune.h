@@ -20,15 +20,17 @@ struct LaunchShape {
     int lds;
 };
 
-// Variants: 0 = automatic (LDS bytes when they fit, else nibbles, else HBM;
-// each wavefront gathers its own shell's offsets); 1 = LDS nibbles when they
-// fit, else HBM; 2 = always HBM; 3 = the automatic shape (kept as an explicit
+// Variants: 0 = automatic (of LDS bytes, LDS nibbles and HBM, the store whose
+// room for steps per pass gives the best measured rate; each wavefront gathers
+// its own shell's offsets); 1 = LDS nibbles or HBM, chosen the same way; 2 =
+// always HBM; 3 = the automatic shape (kept as an explicit
 // name); 4 = automatic store, every wavefront of a slot group gathers an equal
 // share of all offsets and the shells' partial histograms meet in LDS;
 // 5 = the automatic shape with DISJOINT commits decided one by one; 6 = the
 // automatic shape with speculative commit chunks of 4.  The block size follows the
 // number of chains launched together (n_chains) so that all can be resident;
-// the steps per pass are the largest (up to 4) that fit it, unless forced.
+// the steps per pass are the largest (up to 8) that fit it and the store, unless
+// forced.
 // Every variant gives bit-identical results.
 constexpr int kNumStoreVariants = 7;
 

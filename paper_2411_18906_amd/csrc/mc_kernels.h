@@ -98,6 +98,19 @@ hipError_t launch_objective_epilogue(const EvalDesc &ed, int64_t K, const int32_
 hipError_t launch_trial_eval(const EvalDesc &ed, const int8_t *species, const int32_t *counts,
                              const double *target, const double *weight, int64_t n_pairs,
                              const int32_t *pairs, double *dS, int32_t *dN, hipStream_t stream);
+// Random solutions of the global search: configuration c of n_configs is pool
+// slot d.slot0 + c (out [n_configs][N]); d.prefix[j] = sum of the first j
+// species counts (prefix[M] = N).
+struct RandomConfigDesc {
+    uint64_t seed;
+    uint32_t iteration;
+    uint32_t slot0;
+    int32_t M;
+    uint32_t prefix[9];
+};
+hipError_t launch_random_configs(uint32_t N, const RandomConfigDesc &d, int n_configs, int8_t *out,
+                                 hipStream_t stream);
+
 hipError_t launch_philox(const uint32_t *ctr, uint64_t seed, int64_t n, uint32_t *out,
                          hipStream_t stream);
 

@@ -366,4 +366,59 @@ hipError_t launch_philox(const uint32_t *ctr, uint64_t seed, int64_t n, uint32_t
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Random solutions of the global search (Sec. 5.1): the composition-sorted
+// species list placed through a keyed permutation of the sites.  The
+// permutation is a four-round balanced Feistel network on 2h-bit values whose
+// round function is word 0 of Philox4x32-10(counter = (right half, round,
+// slot, 0x80000000 | iteration), key = seed), re-applied (cycle walking) until
+// the value is below N.  One thread per list position.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t feistel4(uint32_t x, int h, uint32_t slot, uint32_t iteration, uint32_t k0,
+                                             uint32_t k1) {
+    const uint32_t mask = (1u << h) - 1u;
+    uint32_t l = x >> h, r = x & mask;
+#pragma unroll
+    for (uint32_t round = 0; round < 4; ++round) {
+        uint32_t c[4] = {r, round, slot, 0x80000000u | iteration};
+        philox4x32_10(c, k0, k1);
+        const uint32_t nl = r;
+        r = l ^ (c[0] & mask);
+        l = nl;
+    }
+    return (l << h) | r;
+}
+
+__global__ void random_configs_kernel(uint32_t N, int h, RandomConfigDesc d, int8_t *__restrict__ out) {
+    const uint32_t cfg = blockIdx.y;
+    const uint32_t slot = d.slot0 + cfg;
+    const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
+    int8_t *o = out + (int64_t)cfg * N;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        int j = 0;
+        while (j + 1 < d.M && i >= d.prefix[j + 1]) ++j;
+        uint32_t x = feistel4(i, h, slot, d.iteration, k0, k1);
+        while (x >= N) x = feistel4(x, h, slot, d.iteration, k0, k1);
+        o[x] = (int8_t)j;
+    }
+}
+
+hipError_t launch_random_configs(uint32_t N, const RandomConfigDesc &d, int n_configs, int8_t *out,
+                                 hipStream_t stream) {
+    if (n_configs <= 0 || N == 0) return hipSuccess;
+    int h = 1;
+    while ((uint64_t(1) << (2 * h)) < N) ++h;
+    const int threads = 256;
+    const int bx = (int)std::min<uint32_t>((N + threads - 1) / threads, 1024);
+    for (int c0 = 0; c0 < n_configs; c0 += 65535) {
+        RandomConfigDesc dc = d;
+        dc.slot0 = d.slot0 + (uint32_t)c0;
+        const int nc = std::min(65535, n_configs - c0);
+        hipLaunchKernelGGL(random_configs_kernel, dim3(bx, nc), dim3(threads), 0, stream, N, h, dc,
+                           out + (int64_t)c0 * N);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace pyhea
