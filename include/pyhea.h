@@ -102,8 +102,8 @@ typedef struct {
     int64_t log_len;     /* accepted-swap records written (min(commits, cap))  */
 } pyhea_mc_stats;
 
-/* Global search parameters (Sec. 5.1, Algorithm 1; the parameter study of
- * Sec. 2.3 names the pool size, the global iterations, the tasks and the
+/* Global search parameters (Sec. 4.1, Algorithm 1; the parameter study of
+ * Sec. 2.1 names the pool size, the global iterations, the tasks and the
  * search depth). */
 typedef struct {
     int32_t n_solutions;   /* solutions in the pool, >= 1                          */
@@ -254,7 +254,7 @@ pyhea_status pyhea_serve_counters(void *server, int64_t *out8_host);
 pyhea_status pyhea_serve_close(void *server);
 
 /*
- * Global search (Sec. 5.1, Algorithm 1).  Iteration t: solutions without a
+ * Global search (Sec. 4.1, Algorithm 1).  Iteration t: solutions without a
  * retained seed are drawn at random (pyhea_random_configs with iteration t);
  * every pool solution is evaluated in full (Eq. 3); the n_refine best (by F,
  * then pool slot) are refined by the Monte Carlo local search of
@@ -274,7 +274,7 @@ pyhea_status pyhea_global_search(const pyhea_lattice *lat, const pyhea_objective
                                  void *stream);
 
 /*
- * Random solutions of the global search (Sec. 5.1: new candidate
+ * Random solutions of the global search (Sec. 4.1: new candidate
  * configurations; the paper does not say how they are drawn).  Configuration
  * c (0 <= c < n_configs) is pool slot slot0 + c of iteration `iteration`: the
  * species list sorted by species (composition_host[j] copies of j) placed on

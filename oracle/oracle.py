@@ -214,7 +214,7 @@ def global_search(lattice: int, L, M: int, S: int, target, weight, composition, 
                   n_solutions: int, iterations: int, n_refine: int, discard_frac: float,
                   seed: int, B: int, n_trials: int, mode: int = MODE_DISJOINT,
                   depth_limit: int = 0, tau: float = 0.0, trace: list | None = None):
-    """Algorithm 1 (Sec. 5.1), in its order:
+    """Algorithm 1 (Sec. 4.1), in its order:
       pool: iteration 0 draws every solution at random; later iterations keep
         the seeds retained by the previous one in slots 0..R-1 and draw new
         random solutions into the rest;

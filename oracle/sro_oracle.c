@@ -576,7 +576,7 @@ int or_mc_run(int lattice, const int *L, int M, int S, const double *target,
 }
 
 /* ------------------------------------------------------------------------ */
-/* New solutions of the global search (Sec. 5.1, Algorithm 1): a random      */
+/* New solutions of the global search (Sec. 4.1, Algorithm 1): a random      */
 /* arrangement of a fixed composition.  The paper does not say how a random  */
 /* configuration is drawn; here position i of the composition-sorted list    */
 /* (species j for c_0 + ... + c_{j-1} <= i < c_0 + ... + c_j) is placed on   */

@@ -367,7 +367,7 @@ hipError_t launch_philox(const uint32_t *ctr, uint64_t seed, int64_t n, uint32_t
 }
 
 // ---------------------------------------------------------------------------
-// Random solutions of the global search (Sec. 5.1): the composition-sorted
+// Random solutions of the global search (Sec. 4.1): the composition-sorted
 // species list placed through a keyed permutation of the sites.  The
 // permutation is a four-round balanced Feistel network on 2h-bit values whose
 // round function is word 0 of Philox4x32-10(counter = (right half, round,

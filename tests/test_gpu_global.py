@@ -1,4 +1,4 @@
-"""Global search (Sec. 5.1, Algorithm 1) and its random solutions on the GPU,
+"""Global search (Sec. 4.1, Algorithm 1) and its random solutions on the GPU,
 against the oracle: bit-exact random configurations, best solution, objective,
 per-iteration history and counters."""
 import numpy as np

@@ -1,4 +1,4 @@
-"""Pins of the oracle's global search (Sec. 5.1, Algorithm 1) and of its random
+"""Pins of the oracle's global search (Sec. 4.1, Algorithm 1) and of its random
 new solutions: properties the algorithm and a random arrangement must have,
 and special cases that reduce to simpler, separately pinned computations."""
 import numpy as np
