@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--serve-jobs", type=int, default=2000, help="served jobs (0 = skip serving)")
     ap.add_argument("--serve-budget-mb", type=int, default=512)
     ap.add_argument("--no-global", action="store_true", help="skip the global search leg")
+    ap.add_argument("--no-baseline", action="store_true", help="skip the incremental-vs-full leg")
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered load / batched capacity")
     return ap.parse_args()
 
@@ -177,6 +178,43 @@ def global_search(pb, p, torch):
     return {"s": dt, "evaluations": st["evaluations"], "trials": st["trials"], "commits": st["commits"],
             "trials_per_s": st["trials"] / dt, "best_F": st["F"], "best_F_per_iteration": [float(x) for x in hist],
             "preset": "64 solutions, 6 iterations, 32 refined (<= 1e5 trials, depth 8, B = 64), p_a = 0.5"}
+
+
+def incremental_vs_full(pb, p, torch, out):
+    """The paper's incremental-versus-full comparison on the FCC 20^3 problem:
+    dS of random swaps from two full evaluations per swap (the baseline) --
+    4,096 swaps per call (throughput) and 64 per call (one MC step of B = 64) --
+    against the incremental recount of the MC kernel (the FCC 20^3 chain and
+    the 512 batched chains of this run) and of the standalone pyhea_trial_eval."""
+    rng = np.random.default_rng(17)
+    n = 4096
+    pairs = torch.from_numpy(rng.integers(0, p.N, size=(n, 2)).astype(np.int32)).cuda()
+    sp = torch.from_numpy(p.species).cuda()
+    dS_i = torch.zeros(n, dtype=torch.float64, device="cuda")
+    dS_f = torch.zeros(n, dtype=torch.float64, device="cuda")
+
+    def timed(fn, reps, per):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps / per * 1e9
+
+    args = (p.lattice, p.L, p.M, p.S, sp, p.target, p.weight)
+    full = timed(lambda: pb.pyhea_trial_eval_full(*args, pairs, dS_f), 3, n)
+    full64 = timed(lambda: pb.pyhea_trial_eval_full(*args, pairs[:64], dS_f[:64]), 20, 64)
+    inc = timed(lambda: pb.pyhea_trial_eval(*args, pairs, dS_i), 3, n)
+    res = {"full_ns_per_swap": full, "full_ns_per_swap_64_per_call": full64,
+           "trial_eval_ns_per_swap": inc, "max_abs_dS_difference": (dS_i - dS_f).abs().max().item()}
+    if out.get("value"):
+        res["chain_ns_per_trial"] = 1e9 / out["value"]
+        res["chain_reduction_vs_full_64"] = 1.0 - res["chain_ns_per_trial"] / full64
+    if "batched" in out:
+        res["batched_ns_per_trial"] = 1e9 / out["batched"]["trials_per_s"]
+        res["batched_reduction_vs_full"] = 1.0 - res["batched_ns_per_trial"] / full
+    return res
 
 
 def main():
@@ -368,6 +406,8 @@ def main():
         out["serving"] = serve(pb, wl, args.serve_jobs, cap, args.serve_load, args.serve_budget_mb)
     if not args.no_global:
         out["global_search"] = global_search(pb, p, torch)
+    if not args.no_baseline:
+        out["incremental_vs_full"] = incremental_vs_full(pb, p, torch, out)
     if "value" not in out:
         out["value"] = None
     if not args.no_cpu_baseline:

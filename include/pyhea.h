@@ -179,6 +179,20 @@ pyhea_status pyhea_trial_eval(const pyhea_lattice *lat, const pyhea_objective *o
                               double *dS_dev, int32_t *dN_dev, void *stream);
 
 /*
+ * Non-incremental baseline of the same quantity (Sec. 4.5: the full
+ * recalculation that Eq. 4 replaces): for each pair (p, q), dS = S(after) -
+ * S(before), each S from a full evaluation (Eq. 2-3) -- of the configuration,
+ * and of a copy with sites p and q swapped.  A pair with equal species gives
+ * dS = 0.  Not bitwise equal to pyhea_trial_eval (a different summation).
+ *   pairs_dev  [n][2] int32 site ids in [0, N), device.
+ *   dS_dev     [n] double, device.
+ * Device scratch of up to 256 MB of swapped copies per call.  Synchronous.
+ */
+pyhea_status pyhea_trial_eval_full(const pyhea_lattice *lat, const pyhea_objective *obj,
+                                   const int8_t *species_dev, int64_t n_pairs, const int32_t *pairs_dev,
+                                   double *dS_dev, void *stream);
+
+/*
  * One Monte Carlo chain (Sec. 4.2, Algorithms 2-3; Sec. 4.6), run as one
  * persistent kernel.  Every step draws B trial swaps from Philox4x32-10 with
  * counter (slot, step, chain_id, 0): p = (x0 * N) >> 32, q = (x1 * N) >> 32;

@@ -164,6 +164,17 @@ def swap_dS(lattice: int, L, M: int, S: int, species: np.ndarray, p: int, q: int
     return float(lib().or_swap_dS(lattice, _p(_L(L)), M, S, _p(sp), p, q, _p(t), _p(w)))
 
 
+def swap_dS_recount(lattice: int, L, M: int, S: int, species: np.ndarray, p: int, q: int, target,
+                    weight) -> float:
+    """dS of swapping sites p and q from two full evaluations (Eq. 2-3):
+    S(after) - S(before), the recalculation the incremental update replaces."""
+    sp = np.array(species, dtype=np.int8, copy=True)
+    _, _, S0, _ = alpha_objective(lattice, L, M, S, sp, counts(lattice, L, M, S, sp), target, weight)
+    sp[p], sp[q] = sp[q], sp[p]
+    _, _, S1, _ = alpha_objective(lattice, L, M, S, sp, counts(lattice, L, M, S, sp), target, weight)
+    return S1 - S0
+
+
 def philox4x32_10(ctr, key) -> np.ndarray:
     c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(4))
     k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(2))

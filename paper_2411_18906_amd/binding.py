@@ -27,7 +27,7 @@ EXPORTS = [
     "pyhea_serve_submit", "pyhea_serve_poll", "pyhea_serve_cancel", "pyhea_serve_counters",
     "pyhea_serve_close", "pyhea_philox4x32_10", "pyhea_tune_force",
     "pyhea_tune_force_eval", "pyhea_tune_force_lookahead", "pyhea_global_search",
-    "pyhea_random_configs",
+    "pyhea_random_configs", "pyhea_trial_eval_full",
 ]
 
 
@@ -108,6 +108,7 @@ def lib():
             "pyhea_tune_force_lookahead": ([i32], i32),
             "pyhea_global_search": ([P, P, P, P, P, P, P, P], i32),
             "pyhea_random_configs": ([i64, i32, P, u64, ctypes.c_uint32, ctypes.c_uint32, i32, P, P], i32),
+            "pyhea_trial_eval_full": ([P, P, P, i64, P, P, P], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -210,6 +211,17 @@ def pyhea_trial_eval(lattice: int, L, M: int, S: int, species, target, weight, p
                                   pairs.shape[0], _dptr(pairs, torch.int32), _dptr(dS, torch.float64),
                                   _dptr(dN, torch.int32) if dN is not None else None,
                                   _stream(stream)))
+
+
+def pyhea_trial_eval_full(lattice: int, L, M: int, S: int, species, target, weight, pairs, dS, stream=None):
+    """dS of each swap from full evaluations before and after (the
+    non-incremental baseline)."""
+    import torch
+    lat = make_lattice(lattice, L, M, S)
+    obj = _Obj(target, weight, S, M)
+    _check(lib().pyhea_trial_eval_full(ctypes.byref(lat), ctypes.byref(obj.c), _dptr(species, torch.int8),
+                                       pairs.shape[0], _dptr(pairs, torch.int32), _dptr(dS, torch.float64),
+                                       _stream(stream)))
 
 
 def pyhea_mc_run(lattice: int, L, M: int, S: int, target, weight, species, params: McParams,

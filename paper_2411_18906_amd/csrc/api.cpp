@@ -265,6 +265,66 @@ pyhea_status pyhea_mc_batch(int32_t n_chains, const pyhea_lattice *lats, const p
     return s == PYHEA_OK ? guard(s) : s;
 }
 
+pyhea_status pyhea_trial_eval_full(const pyhea_lattice *lat, const pyhea_objective *obj, const int8_t *species_dev,
+                                   int64_t n_pairs, const int32_t *pairs_dev, double *dS_dev, void *stream_) {
+    Geometry g;
+    std::string err;
+    if (build_geometry(lat, &g, &err) != PYHEA_OK) {
+        set_error(err);
+        return PYHEA_EINVAL;
+    }
+    pyhea_status s = check_objective(g, obj);
+    if (s != PYHEA_OK) return s;
+    if (n_pairs < 0 || !species_dev || (n_pairs > 0 && (!pairs_dev || !dS_dev))) {
+        set_error("n_pairs must be >= 0 and species/pairs/dS pointers non-NULL");
+        return PYHEA_EINVAL;
+    }
+    hipStream_t stream = as_stream(stream_);
+    const int64_t N = g.N;
+    const int E = g.S * g.M * g.M;
+    // swapped copies in chunks of at most 256 MB
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_pairs, (int64_t(256) << 20) / N));
+    const size_t o_cnt = ((size_t)chunk * N + 255) & ~size_t(255);
+    const size_t o_sf = (o_cnt + (size_t)chunk * E * 4 + 255) & ~size_t(255);
+    const size_t o_s0 = o_sf + (size_t)chunk * 16;
+    const size_t o_bad = o_s0 + 16;
+    AsyncBuffer buf;
+    buf.stream = stream;
+    PYHEA_HIP(pool_alloc(&buf.ptr, o_bad + 256, stream));
+    char *base = (char *)buf.ptr;
+    int8_t *copies = (int8_t *)base;
+    int32_t *counts = (int32_t *)(base + o_cnt);
+    double *SF = (double *)(base + o_sf);
+    double *S0 = (double *)(base + o_s0);
+    int32_t *bad = (int32_t *)(base + o_bad);
+    PYHEA_HIP(launch_upload(SmallTable{}, 1, (double *)bad, stream));   // clears the flag word
+    // S(before) from a full evaluation of the configuration itself
+    s = pyhea_sro_eval_batch(lat, 1, species_dev, obj, counts, S0, stream);
+    if (s != PYHEA_OK) return s;
+    double s0h[2];
+    PYHEA_HIP(hipMemcpyAsync(s0h, S0, 16, hipMemcpyDeviceToHost, stream));
+    PYHEA_HIP(hipStreamSynchronize(stream));
+    if (std::isnan(s0h[0])) {
+        set_error("species ids must lie in [0, n_species) and every species must occur");
+        return PYHEA_EINVAL;
+    }
+    for (int64_t c0 = 0; c0 < n_pairs; c0 += chunk) {
+        const int nc = (int)std::min<int64_t>(chunk, n_pairs - c0);
+        PYHEA_HIP(launch_swap_copies(species_dev, N, pairs_dev + 2 * c0, nc, copies, bad, stream));
+        s = pyhea_sro_eval_batch(lat, nc, copies, obj, counts, SF, stream);
+        if (s != PYHEA_OK) return s;
+        PYHEA_HIP(launch_sub_objective(SF, S0, nc, dS_dev + c0, stream));
+    }
+    int32_t badh = 0;
+    PYHEA_HIP(hipMemcpyAsync(&badh, bad, 4, hipMemcpyDeviceToHost, stream));
+    PYHEA_HIP(hipStreamSynchronize(stream));
+    if (badh) {
+        set_error("site ids must lie in [0, N)");
+        return PYHEA_EINVAL;
+    }
+    return guard(PYHEA_OK);
+}
+
 static pyhea_status random_desc(int64_t N, int32_t M, const int64_t *comp, uint64_t seed, uint32_t iteration,
                                 uint32_t slot0, RandomConfigDesc *d) {
     if (N < 1 || N > (int64_t(1) << 30) || M < 1 || M > 8 || !comp) {

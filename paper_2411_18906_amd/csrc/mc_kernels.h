@@ -98,6 +98,12 @@ hipError_t launch_objective_epilogue(const EvalDesc &ed, int64_t K, const int32_
 hipError_t launch_trial_eval(const EvalDesc &ed, const int8_t *species, const int32_t *counts,
                              const double *target, const double *weight, int64_t n_pairs,
                              const int32_t *pairs, double *dS, int32_t *dN, hipStream_t stream);
+// Non-incremental baseline: out[i] = base with sites pairs[i] swapped (out
+// [n][N]); *bad |= 1 for a pair outside [0, N).  dS[i] = S_F[i][0] - S0[0].
+hipError_t launch_swap_copies(const int8_t *base, int64_t N, const int32_t *pairs, int n, int8_t *out, int32_t *bad,
+                              hipStream_t stream);
+hipError_t launch_sub_objective(const double *S_F, const double *S0, int n, double *dS, hipStream_t stream);
+
 // Random solutions of the global search: configuration c of n_configs is pool
 // slot d.slot0 + c (out [n_configs][N]); d.prefix[j] = sum of the first j
 // species counts (prefix[M] = N).

@@ -421,4 +421,61 @@ hipError_t launch_random_configs(uint32_t N, const RandomConfigDesc &d, int n_co
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Non-incremental baseline: copies of one configuration with one swap each.
+// ---------------------------------------------------------------------------
+
+__global__ void replicate_kernel(const int8_t *__restrict__ base, int64_t N, int n, int8_t *__restrict__ out) {
+    const int64_t row = blockIdx.y;
+    int8_t *o = out + row * N;
+    if ((N & 3) == 0) {
+        const uint32_t *b4 = reinterpret_cast<const uint32_t *>(base);
+        uint32_t *o4 = reinterpret_cast<uint32_t *>(o);
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N / 4; i += (int64_t)gridDim.x * blockDim.x)
+            o4[i] = b4[i];
+    } else {
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+            o[i] = base[i];
+    }
+}
+
+// pair i swaps sites p, q of copy i; a pair outside [0, N) sets *bad and is skipped
+__global__ void apply_swaps_kernel(const int8_t *__restrict__ base, int64_t N, const int32_t *__restrict__ pairs,
+                                   int n, int8_t *__restrict__ out, int32_t *__restrict__ bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t p = pairs[2 * i], q = pairs[2 * i + 1];
+    if (p < 0 || q < 0 || p >= N || q >= N) {
+        atomicOr(bad, 1);
+        return;
+    }
+    out[(int64_t)i * N + p] = base[q];
+    out[(int64_t)i * N + q] = base[p];
+}
+
+__global__ void sub_objective_kernel(const double *__restrict__ S_F, const double *__restrict__ S0, int n,
+                                     double *__restrict__ dS) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dS[i] = S_F[2 * i] - S0[0];
+}
+
+hipError_t launch_swap_copies(const int8_t *base, int64_t N, const int32_t *pairs, int n, int8_t *out, int32_t *bad,
+                              hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t words = (N & 3) == 0 ? N / 4 : N;
+    const int bx = (int)std::min<int64_t>((words + 255) / 256, 256);
+    for (int r0 = 0; r0 < n; r0 += 65535) {
+        const int nr = std::min(65535, n - r0);
+        hipLaunchKernelGGL(replicate_kernel, dim3(bx, nr), dim3(256), 0, stream, base, N, nr, out + (int64_t)r0 * N);
+    }
+    hipLaunchKernelGGL(apply_swaps_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, base, N, pairs, n, out, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub_objective(const double *S_F, const double *S0, int n, double *dS, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sub_objective_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, S_F, S0, n, dS);
+    return hipGetLastError();
+}
+
 }  // namespace pyhea

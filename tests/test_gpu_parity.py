@@ -143,6 +143,33 @@ def test_trial_eval_matches_oracle(shape):
         assert ds[u] == orc.swap_dS(lattice, L, M, S, sp, int(p), int(q), tgt, w)
 
 
+@pytest.mark.parametrize("shape", SHAPES[:9])
+def test_trial_eval_full_matches_oracle(shape):
+    # the non-incremental baseline: two full evaluations per swap
+    lattice, L, M, S = shape
+    rng = np.random.default_rng(8)
+    sp, tgt, w = random_problem(rng, lattice, L, M, S)
+    N = len(sp)
+    pairs = rng.integers(0, N, size=(40, 2)).astype(np.int32)
+    pairs[:3, 1] = pairs[:3, 0]        # p == q
+    dS = torch.zeros(40, dtype=torch.float64, device="cuda")
+    pb.pyhea_trial_eval_full(lattice, L, M, S, dev(sp), tgt, w, dev(pairs), dS)
+    ds = dS.cpu().numpy()
+    for u, (p, q) in enumerate(pairs):
+        assert ds[u] == orc.swap_dS_recount(lattice, L, M, S, sp, int(p), int(q), tgt, w)
+
+
+def test_trial_eval_full_rejects_bad_pairs():
+    lattice, L, M, S = orc.FCC, (3, 3, 3), 3, 2
+    rng = np.random.default_rng(1)
+    sp, tgt, w = random_problem(rng, lattice, L, M, S)
+    pairs = np.array([[0, 1], [2, len(sp)]], np.int32)
+    dS = torch.zeros(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(pb.PyheaError) as e:
+        pb.pyhea_trial_eval_full(lattice, L, M, S, dev(sp), tgt, w, dev(pairs), dS)
+    assert e.value.code == pb.EINVAL
+
+
 def run_both(lattice, L, M, S, sp, tgt, w, *, seed, chain, T, B, mode=0, depth=0, tau=0.0):
     sp_o, log_o, st_o, cnt_o = orc.mc_run(lattice, L, M, S, tgt, w, sp, seed=seed, chain_id=chain,
                                           n_trials=T, B=B, mode=mode, depth_limit=depth, tau=tau)
