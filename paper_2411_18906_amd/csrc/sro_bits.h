@@ -15,6 +15,7 @@ struct BitDesc {
     int32_t PW;        // LW + 2 * PADW
     int32_t cw0, NCW;  // words that hold centre sites
     int32_t nchx;      // 32-position chunks per padded row (RS bits)
+    int32_t vec4;      // rows read as 16-byte blocks (Lx % 4 == 0, 16-byte aligned configurations)
     int32_t ZC;        // centre layers per workgroup
     int32_t nchunks;   // workgroups per configuration
     int32_t threads;   // workgroup size

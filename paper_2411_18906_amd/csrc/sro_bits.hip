@@ -177,7 +177,8 @@ __device__ __forceinline__ void lds_planes(const uint32_t *p, uint32_t *v) {
 // MaxW: the wavefronts per SIMD the register allocation aims for -- 4 for a
 // workgroup alone on its CU (registers spent on overlapping loads), 8 when
 // several workgroups share the CU.
-template <int M, int S, int MaxW>
+// V4: rows read as 16-byte blocks (Lx % 4 == 0 and a 16-byte aligned batch).
+template <int M, int S, int MaxW, bool V4>
 __global__ void __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(4, MaxW)))
 count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int32_t *__restrict__ partial,
                   int32_t *__restrict__ counts_out, int32_t *__restrict__ bad_out, const double *__restrict__ tw,
@@ -249,6 +250,43 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
             for (int g = 0; g < 4; ++g)
 #pragma unroll
                 for (int j = 0; j < P; ++j) acc[j][g] = 0;
+            if constexpr (V4) {
+                // rows of whole 16-byte blocks: block t of the window is block
+                // 8 cxc - 1 + t (mod Lx / 4) of the row, and padded column pos of
+                // the chunk (cell 32 cxc + pos - 1) is word (pos + 3) & 3 of window
+                // block (pos + 3) >> 2.  Two halves of 16 columns, five blocks each
+                // (the last block of the first half is the first of the second).
+                const int nb = bd.Lx >> 2;
+                uint4 blk[5];
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    if (32 * cxc + 16 * half >= RS) break;   // uniform
+                    // keep the second half's loads after the first half's use of
+                    // its blocks (bounds the registers held by loads in flight)
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (half == 1) blk[0] = blk[4];
+#pragma unroll
+                    for (int t = half; t < 5; ++t) {
+                        int k = 8 * cxc - 1 + 4 * half + t;
+                        k = k < 0 ? k + nb : k;
+                        while (k >= nb) k -= nb;
+                        blk[t] = *reinterpret_cast<const uint4 *>(cfg + (rowoff + 16u * (uint32_t)k));
+                    }
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int t = (q + 3) >> 2, w = (q + 3) & 3;
+                        const uint32_t d = w == 0 ? blk[t].x : w == 1 ? blk[t].y : w == 2 ? blk[t].z : blk[t].w;
+                        const int g = 2 * half + (q >> 3), m = q & 7;
+                        badacc |= d | (d + kBad);
+#pragma unroll
+                        for (int j = 0; j < P; ++j) {
+                            const uint64_t lut = 1ull << (8 * j);
+                            acc[j][g] |= perm((uint32_t)(lut >> 32), (uint32_t)lut, d) << m;
+                        }
+                        if (q & 1) __builtin_amdgcn_sched_barrier(0);   // two columns at a time
+                    }
+                }
+            } else {
             // padded column pos holds cell (pos - 1) mod Lx; columns past the row
             // end read cell 0 and are masked below, so every load is in bounds.
             // GF groups of 8 loads are issued before any of them is used.
@@ -282,6 +320,7 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
                         }
                     }
                 }
+            }
             }
             // 4x4 byte transpose: acc[j][g] byte b = bits of positions 8g..8g+7 of sublattice b
             const int o = fy * RS + 32 * cxc;
@@ -447,8 +486,11 @@ hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_
     const size_t lds = ((size_t)(bd.ZC + 1) * 4 * P * bd.PW + bd.LW + NV * 64 + NV + 1 + 8 * bd.nh + 1 +
                         3 * S * M * M + 2 * S * M + 2) * 4;
     const bool lone = bd.threads > 512;   // one workgroup per CU
-    const void *fn = lone ? (const void *)count_bits_kernel<M, S, 4> : (const void *)count_bits_kernel<M, S, 8>;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    using KernelFn = void (*)(BitDesc, int64_t, const int8_t *, int32_t *, int32_t *, int32_t *, const double *,
+                              double *);
+    const KernelFn fn = lone ? (bd.vec4 ? count_bits_kernel<M, S, 4, true> : count_bits_kernel<M, S, 4, false>)
+                             : (bd.vec4 ? count_bits_kernel<M, S, 8, true> : count_bits_kernel<M, S, 8, false>);
+    hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (bd.nchunks > 1) {
         const int64_t n = K * bd.partial_stride;
@@ -457,14 +499,9 @@ hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_
     }
     for (int64_t k0 = 0; k0 < K; k0 += 65535) {
         const int64_t kn = std::min<int64_t>(65535, K - k0);
-        if (!lone)
-            hipLaunchKernelGGL((count_bits_kernel<M, S, 8>), dim3(bd.nchunks, (unsigned)kn), dim3(bd.threads), lds, stream,
-                               bd, kn, species + k0 * (int64_t)bd.N, partial + k0 * bd.partial_stride,
-                               counts + k0 * (int64_t)(S * M * M), bad + k0, tw, S_F ? S_F + 2 * k0 : nullptr);
-        else
-            hipLaunchKernelGGL((count_bits_kernel<M, S, 4>), dim3(bd.nchunks, (unsigned)kn), dim3(bd.threads), lds, stream,
-                               bd, kn, species + k0 * (int64_t)bd.N, partial + k0 * bd.partial_stride,
-                               counts + k0 * (int64_t)(S * M * M), bad + k0, tw, S_F ? S_F + 2 * k0 : nullptr);
+        hipLaunchKernelGGL(fn, dim3(bd.nchunks, (unsigned)kn), dim3(bd.threads), lds, stream, bd, kn,
+                           species + k0 * (int64_t)bd.N, partial + k0 * bd.partial_stride,
+                           counts + k0 * (int64_t)(S * M * M), bad + k0, tw, S_F ? S_F + 2 * k0 : nullptr);
     }
     if (bd.nchunks > 1 && S_F)
         hipLaunchKernelGGL((finalize_objective_kernel<M, S>), dim3((unsigned)K), dim3(64), 0, stream, bd, partial,
@@ -574,7 +611,9 @@ hipError_t launch_count_bits(const Geometry &g, const BitDesc &bd, int64_t K, co
                              hipStream_t stream) {
     LaunchFn f = pick(g.M, g.S);
     if (!f) return hipErrorInvalidValue;
-    return f(bd, K, species, partial, counts, bad, tw, S_F, stream);
+    BitDesc b = bd;
+    b.vec4 = bd.Lx % 4 == 0 && (reinterpret_cast<uintptr_t>(species) & 15) == 0 ? 1 : 0;
+    return f(b, K, species, partial, counts, bad, tw, S_F, stream);
 }
 
 }  // namespace pyhea
