@@ -241,6 +241,30 @@ def pyhea_mc_run(lattice: int, L, M: int, S: int, target, weight, species, param
     return st.as_dict(), counts
 
 
+_LAT_DTYPE = np.dtype([("lattice", "<i4"), ("L", "<i4", (3,)), ("n_species", "<i4"), ("n_shells", "<i4")])
+
+
+def _batch_descriptors(problems):
+    """Lattice array, objective pointer array and the host block they point
+    into, for n problems, built with a few numpy calls."""
+    n = len(problems)
+    lat = np.array([(p[0], tuple(p[1]), p[2], p[3]) for p in problems], dtype=_LAT_DTYPE)
+    parts = []
+    for p in problems:
+        parts.append(np.asarray(p[4], dtype=np.float64).reshape(-1))
+        parts.append(np.asarray(p[5], dtype=np.float64).reshape(-1))
+    block = np.ascontiguousarray(np.concatenate(parts))
+    S = lat["n_shells"].astype(np.int64)
+    E = S * lat["n_species"].astype(np.int64) ** 2
+    start = np.concatenate([[0], np.cumsum(E + S)])
+    if block.size != start[-1]:
+        raise ValueError("target/weight sizes do not match the problems' S and M")
+    obj = np.empty((n, 2), np.uint64)
+    obj[:, 0] = block.ctypes.data + 8 * start[:-1]
+    obj[:, 1] = block.ctypes.data + 8 * (start[:-1] + E)
+    return lat, obj, block
+
+
 def pyhea_mc_batch(problems, species, offsets, params_list, log=None, log_offsets=None,
                    stream=None):
     """Many chains in one call.  problems: list of (lattice, L, M, S, target,
@@ -248,16 +272,15 @@ def pyhea_mc_batch(problems, species, offsets, params_list, log=None, log_offset
     Returns a list of stats dicts."""
     import torch
     n = len(problems)
-    lats = (Lattice * n)(*[make_lattice(p[0], p[1], p[2], p[3]) for p in problems])
-    keep = [_Obj(p[4], p[5], p[3], p[2]) for p in problems]
-    objs = (Objective * n)(*[k.c for k in keep])
+    lat, obj, block = _batch_descriptors(problems)
     pars = (McParams * n)(*params_list)
     stats = (McStats * n)()
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
     loff = None if log_offsets is None else np.ascontiguousarray(np.asarray(log_offsets, np.int64))
-    _check(lib().pyhea_mc_batch(n, lats, objs, pars, _dptr(species, torch.int8), _hptr(off),
+    _check(lib().pyhea_mc_batch(n, _hptr(lat), _hptr(obj), pars, _dptr(species, torch.int8), _hptr(off),
                                 _dptr(log, torch.int32) if log is not None else None,
                                 _hptr(loff), stats, _stream(stream)))
+    del block
     return [s.as_dict() for s in stats]
 
 
