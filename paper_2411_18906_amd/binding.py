@@ -269,7 +269,8 @@ def pyhea_mc_batch(problems, species, offsets, params_list, log=None, log_offset
                    stream=None):
     """Many chains in one call.  problems: list of (lattice, L, M, S, target,
     weight); species: device int8, chains concatenated; offsets: [n+1] int64.
-    Returns a list of stats dicts."""
+    Returns the per-chain stats as a numpy structured array (fields of
+    pyhea_mc_stats: stats[i]["F"], ...)."""
     import torch
     n = len(problems)
     lat, obj, block = _batch_descriptors(problems)
@@ -281,7 +282,7 @@ def pyhea_mc_batch(problems, species, offsets, params_list, log=None, log_offset
                                 _dptr(log, torch.int32) if log is not None else None,
                                 _hptr(loff), stats, _stream(stream)))
     del block
-    return [s.as_dict() for s in stats]
+    return np.ctypeslib.as_array(stats).copy()
 
 
 def pyhea_philox4x32_10(ctr, seed: int, out, stream=None):

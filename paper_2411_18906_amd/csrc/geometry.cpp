@@ -4,6 +4,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace pyhea {
 
@@ -61,7 +64,41 @@ int32_t padded_delta(const Geometry &g, int b, int t) {
     return (int32_t)(d * g.A + (bt - b));
 }
 
+namespace {
+pyhea_status build_geometry_uncached(const pyhea_lattice *lat, Geometry *g, std::string *err);
+}
+
+// Geometries are a pure function of the descriptor: built ones are kept (up to
+// 4096 distinct descriptors) so that calls with many chains of few shapes, and
+// repeated calls, skip the shell and offset enumeration.
 pyhea_status build_geometry(const pyhea_lattice *lat, Geometry *g, std::string *err) {
+    using Key = std::tuple<int, int, int, int, int, int>;
+    static std::mutex mu;
+    static std::map<Key, Geometry> cache;
+    if (lat) {
+        const Key key{lat->lattice, lat->L[0], lat->L[1], lat->L[2], lat->n_species, lat->n_shells};
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            auto it = cache.find(key);
+            if (it != cache.end()) {
+                *g = it->second;
+                return PYHEA_OK;
+            }
+        }
+        const pyhea_status s = build_geometry_uncached(lat, g, err);
+        if (s == PYHEA_OK) {
+            std::lock_guard<std::mutex> lock(mu);
+            if (cache.size() >= 4096) cache.clear();
+            cache.emplace(key, *g);
+        }
+        return s;
+    }
+    return build_geometry_uncached(lat, g, err);
+}
+
+namespace {
+
+pyhea_status build_geometry_uncached(const pyhea_lattice *lat, Geometry *g, std::string *err) {
     *g = Geometry();
     if (!lat) {
         *err = "lattice descriptor is NULL";
@@ -148,6 +185,8 @@ pyhea_status build_geometry(const pyhea_lattice *lat, Geometry *g, std::string *
     g->Npad = (int64_t)g->A * g->P[0] * g->P[1] * g->P[2];
     return PYHEA_OK;
 }
+
+}  // namespace
 
 void fill_chain_geometry(const Geometry &g, ChainDesc *d) {
     d->A = g.A;
