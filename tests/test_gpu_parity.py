@@ -159,6 +159,27 @@ def test_trial_eval_full_matches_oracle(shape):
         assert ds[u] == orc.swap_dS_recount(lattice, L, M, S, sp, int(p), int(q), tgt, w)
 
 
+def test_trial_eval_full_chunks_and_empty():
+    # 300 swaps of a 1,048,576-site cell: the swapped copies span two 256 MB chunks
+    lattice, L, M, S = orc.FCC, (64, 64, 64), 4, 2
+    rng = np.random.default_rng(5)
+    N = orc.n_sites(lattice, L)
+    sp = wl.shuffled_config(N, np.full(M, N // M), 99, 0)
+    tgt = wl.projected_target(S, M, np.full(M, 1.0 / M), 7)
+    w = np.array([1.0, 0.5])
+    pairs = rng.integers(0, N, size=(300, 2)).astype(np.int32)
+    dS = torch.full((300,), np.nan, dtype=torch.float64, device="cuda")
+    d = dev(sp)
+    pb.pyhea_trial_eval_full(lattice, L, M, S, d, tgt, w, dev(pairs), dS)
+    ds = dS.cpu().numpy()
+    assert not np.isnan(ds).any()
+    for u in [0, 255, 256, 299]:
+        p, q = (int(x) for x in pairs[u])
+        assert ds[u] == orc.swap_dS_recount(lattice, L, M, S, sp, p, q, tgt, w)
+    empty = torch.zeros(0, dtype=torch.float64, device="cuda")
+    pb.pyhea_trial_eval_full(lattice, L, M, S, d, tgt, w, dev(pairs[:0]), empty)
+
+
 def test_trial_eval_full_rejects_bad_pairs():
     lattice, L, M, S = orc.FCC, (3, 3, 3), 3, 2
     rng = np.random.default_rng(1)
