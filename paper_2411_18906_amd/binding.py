@@ -145,7 +145,8 @@ def _dptr(t, dtype=None):
 
 
 def _hptr(a: np.ndarray | None):
-    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    # the array interface's address (numpy's .ctypes helper object costs ~17 us)
+    return None if a is None else ctypes.c_void_p(a.__array_interface__["data"][0])
 
 
 def make_lattice(lattice: int, L, M: int, S: int) -> Lattice:

@@ -36,6 +36,10 @@ inline int64_t species_store_bytes(int store, int64_t Npad) {
     return 0;
 }
 
+// Raises a kernel's dynamic LDS limit to at least `lds` bytes on the current
+// device; remembers what it set, so repeated launches make no runtime call.
+hipError_t set_max_lds(const void *fn, size_t lds);
+
 // Wavefronts of one chain's block: K steps x slot groups x W.
 inline int mc_block_waves(int B, int W, int K) { return K * ((B + 63) / 64) * W; }
 int mc_block_threads(int B, int W, int K);

@@ -967,7 +967,7 @@ hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M,
     const void *fn = store == kStoreLds8 ? mc_fn<kStoreLds8>(M)
                      : store == kStoreLds4 ? mc_fn<kStoreLds4>(M)
                                            : mc_fn<kStoreGlobal>(M);
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    hipError_t e = set_max_lds(fn, lds_bytes);
     if (e != hipSuccess) return e;
     void *args[] = {(void *)&descs_dev, (void *)&max_steps, (void *)&W, (void *)&bal, (void *)&K, (void *)&CH};
     return hipLaunchKernel(fn, grid, block, args, (size_t)lds_bytes, stream);

@@ -44,6 +44,20 @@ hipError_t pool_alloc(void **ptr, size_t bytes, hipStream_t stream) {
     return hipMallocAsync(ptr, bytes, stream);
 }
 
+hipError_t set_max_lds(const void *fn, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, size_t> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = done.find({dev, fn});
+    if (it != done.end() && it->second >= lds) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) done[{dev, fn}] = lds;
+    return e;
+}
+
 int max_lds_per_block() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
@@ -160,7 +174,8 @@ pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, 
     const int split = forced == 2 ? 1 : forced == 3 ? 4 : 2;
     if (forced != 0 && fill_bit_desc(g, max_lds_per_block(), K, split, &bd)) {
         void *partial = nullptr;
-        if (bd.nchunks > 1) PYHEA_HIP(pool_alloc(&partial, (size_t)K * bd.partial_stride * 4, stream));
+        if (bd.nchunks > 1)
+            PYHEA_HIP(pool_alloc(&partial, (size_t)K * bd.nchunks * bd.partial_stride * 4, stream));
         const bool fuse = S_F != nullptr;   // the counting launch finishes Eq. 2-3 too
         const hipError_t e = launch_count_bits(g, bd, K, species, (int32_t *)partial, counts, bad,
                                                fuse ? tw : nullptr, fuse ? S_F : nullptr, stream);

@@ -36,7 +36,7 @@ struct BitDesc {
 bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitDesc *bd);
 
 // counts [K][S][M][M] and bad [K] of K configurations; `partial` is scratch of
-// K * bd.partial_stride int32 (used when a configuration spans several
+// K * bd.nchunks * bd.partial_stride int32 (used when a configuration spans several
 // workgroups).  With S_F != null (and bd.nchunks == 1) the kernel also writes
 // S_F [K][2] from tw = {target [S][M][M], weight [S]} (device).
 hipError_t launch_count_bits(const Geometry &g, const BitDesc &bd, int64_t K, const int8_t *species,

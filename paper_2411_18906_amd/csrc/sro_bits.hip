@@ -27,6 +27,7 @@
 #include <cstring>
 
 #include "device_common.h"
+#include "mc_kernels.h"
 #include "sro_bits.h"
 
 namespace pyhea {
@@ -419,13 +420,9 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
     }
     __syncthreads();
     if (bd.nchunks > 1) {
-        int32_t *out = partial + kc * (int64_t)bd.partial_stride;
-        for (int i = threadIdx.x; i < NV + 1; i += blockDim.x) {
-            if (i < NV)
-                atomicAdd(&out[i], red[i]);
-            else if (red[i])
-                atomicOr(&out[i], red[i]);
-        }
+        // this workgroup's own slot; the finishing kernel adds the slots up
+        int32_t *out = partial + ((int64_t)kc * bd.nchunks + chunk) * bd.partial_stride;
+        for (int i = threadIdx.x; i < NV + 1; i += blockDim.x) out[i] = red[i];
         return;
     }
     // ---- 4. one workgroup holds the whole configuration: counts and Eq. 2-3 here ----
@@ -437,7 +434,19 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
 }
 
 
-// partial sums -> full counts N[k][i][j] (one thread per configuration)
+// The sums of one configuration from its workgroups' slots [nchunks][stride]
+// into sum [NV + 1] (the last entry ORs the bad-species flags).
+template <int M, int S>
+__device__ __forceinline__ void add_slots(const int32_t *slots, const BitDesc &bd, int i0, int di, int32_t *sum) {
+    constexpr int NV = S * Pairs<M>::NP + M - 1;
+    for (int i = i0; i < NV + 1; i += di) {
+        int32_t v = 0;
+        for (int c = 0; c < bd.nchunks; ++c) v = i < NV ? v + slots[c * bd.partial_stride + i] : (v | slots[c * bd.partial_stride + i]);
+        sum[i] = v;
+    }
+}
+
+// slot sums -> full counts N[k][i][j] (one thread per configuration)
 template <int M, int S>
 __global__ void finalize_bits_kernel(BitDesc bd, int64_t K, const int32_t *__restrict__ partial,
                                      int32_t *__restrict__ counts, int32_t *__restrict__ bad) {
@@ -445,7 +454,8 @@ __global__ void finalize_bits_kernel(BitDesc bd, int64_t K, const int32_t *__res
     constexpr int NP = Pairs<M>::NP;
     const int64_t kc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (kc >= K) return;
-    const int32_t *pa = partial + kc * (int64_t)bd.partial_stride;
+    int32_t pa[S * NP + P + 1];
+    add_slots<M, S>(partial + kc * bd.nchunks * (int64_t)bd.partial_stride, bd, 0, 1, pa);
     int32_t *c = counts + kc * (int64_t)(S * M * M);
     int64_t n[M];
     int64_t rest = bd.N;
@@ -458,24 +468,21 @@ __global__ void finalize_bits_kernel(BitDesc bd, int64_t K, const int32_t *__res
     for (int k = 0; k < S; ++k) expand_shell<M>(pa + k * NP, bd.zk[k], n, c + k * M * M);
 }
 
-// partial sums -> counts and Eq. 2-3 (one 64-thread block per configuration)
+// slot sums -> counts and Eq. 2-3 (one 64-thread block per configuration)
 template <int M, int S>
 __global__ void __launch_bounds__(64) finalize_objective_kernel(BitDesc bd, const int32_t *__restrict__ partial,
                                                                int32_t *__restrict__ counts,
                                                                int32_t *__restrict__ bad,
                                                                const double *__restrict__ tw,
                                                                double *__restrict__ S_F) {
+    __shared__ int32_t lsum[S * Pairs<M>::NP + M];
     __shared__ int32_t lc[S * M * M];
     __shared__ double lsq[S * M * M];
     __shared__ double lrow[S * M];
     const int64_t kc = blockIdx.x;
-    epilogue<M, S>(partial + kc * bd.partial_stride, bd, lc, lsq, lrow, counts + kc * (int64_t)(S * M * M), bad + kc,
-                   tw, S_F + 2 * kc);
-}
-
-__global__ void zero_kernel(int32_t *p, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
+    add_slots<M, S>(partial + kc * bd.nchunks * (int64_t)bd.partial_stride, bd, threadIdx.x, blockDim.x, lsum);
+    __syncthreads();
+    epilogue<M, S>(lsum, bd, lc, lsq, lrow, counts + kc * (int64_t)(S * M * M), bad + kc, tw, S_F + 2 * kc);
 }
 
 template <int M, int S>
@@ -490,17 +497,12 @@ hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_
                               double *);
     const KernelFn fn = lone ? (bd.vec4 ? count_bits_kernel<M, S, 4, true> : count_bits_kernel<M, S, 4, false>)
                              : (bd.vec4 ? count_bits_kernel<M, S, 8, true> : count_bits_kernel<M, S, 8, false>);
-    hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = set_max_lds((const void *)fn, lds);
     if (e != hipSuccess) return e;
-    if (bd.nchunks > 1) {
-        const int64_t n = K * bd.partial_stride;
-        hipLaunchKernelGGL(zero_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0,
-                           stream, partial, n);
-    }
     for (int64_t k0 = 0; k0 < K; k0 += 65535) {
         const int64_t kn = std::min<int64_t>(65535, K - k0);
         hipLaunchKernelGGL(fn, dim3(bd.nchunks, (unsigned)kn), dim3(bd.threads), lds, stream, bd, kn,
-                           species + k0 * (int64_t)bd.N, partial + k0 * bd.partial_stride,
+                           species + k0 * (int64_t)bd.N, partial + k0 * bd.nchunks * bd.partial_stride,
                            counts + k0 * (int64_t)(S * M * M), bad + k0, tw, S_F ? S_F + 2 * k0 : nullptr);
     }
     if (bd.nchunks > 1 && S_F)
