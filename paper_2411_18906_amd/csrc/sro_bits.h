@@ -28,7 +28,9 @@ struct BitDesc {
     int32_t tab_r[4][kMaxOffsets / 2];      // funnel-shift amount
 };
 
-// Fills bd; false if the bit-sliced kernel does not cover this geometry.
+// Fills bd; false if the bit-sliced kernel does not cover this geometry (it
+// covers FCC, and BCC with an even number of cells along x, for shells whose
+// neighbours lie at most one cell away).
 // K is the number of configurations of the launch: few configurations are
 // split along z over more workgroups.  With split > 1, a configuration whose
 // layers would take more than 1/split of a CU's LDS is cut along z so that

@@ -1,10 +1,12 @@
-// Bit-sliced full SRO evaluation for FCC supercells (Sec. 4.3, Eq. 2).
+// Bit-sliced full SRO evaluation (Sec. 4.3, Eq. 2) for lattices laid out as
+// cells of four sites: FCC, and BCC with an even number of cells along x (two
+// BCC cells along x form one four-site cell; see fill_bit_desc).
 //
 // One workgroup counts a range of z-layers of one configuration:
 //  1. Conversion.  Per sublattice b and species j < M-1 a layer becomes a flat
 //     bit array with a one-cell periodic border: bit fy * RS + fx (RS = Lx + 2)
 //     holds cell ((fx - 1) mod Lx, (fy - 1) mod Ly).  A lane converts one padded
-//     row: each FCC cell is one dword (4 sublattice bytes), a v_perm lookup maps
+//     row: each cell is one dword (4 sublattice bytes), a v_perm lookup maps
 //     species ids to one-hot bytes, 8 cells are merged per byte lane with
 //     shift-or, and a 4x4 byte transpose yields 32-position bit rows that are
 //     OR-ed into LDS.  The M-1 species planes are interleaved word by word:
@@ -545,12 +547,22 @@ LaunchFn pick(int M, int S) {
 
 bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitDesc *bd) {
     std::memset(bd, 0, sizeof(*bd));
-    if (g.lattice != PYHEA_FCC || g.halo != 1 || !pick(g.M, g.S)) return false;
+    if (g.halo != 1 || !pick(g.M, g.S)) return false;
+    // Cells of four sites: an FCC cell, or two BCC cells along x (site id
+    // ((cz Ly + cy) Lx + cx) 2 + b is ((cz Ly + cy) (Lx/2) + cx/2) 4 + 2 (cx % 2) + b,
+    // so an even-Lx BCC configuration is laid out as cells of four sublattices)
+    int Lx4;
+    if (g.lattice == PYHEA_FCC)
+        Lx4 = g.L[0];
+    else if (g.lattice == PYHEA_BCC && g.L[0] % 2 == 0)
+        Lx4 = g.L[0] / 2;
+    else
+        return false;
     const int P = g.M - 1;
-    bd->Lx = g.L[0];
+    bd->Lx = Lx4;
     bd->Ly = g.L[1];
     bd->Lz = g.L[2];
-    bd->RS = g.L[0] + 2;
+    bd->RS = Lx4 + 2;
     const int bits = (g.L[1] + 2) * bd->RS;
     bd->LW = (bits + 31) / 32;
     bd->PADW = (bd->RS + 2 + 31) / 32 + 1;
@@ -592,7 +604,22 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitD
             if (!keep) continue;
             for (int b = 0; b < 4; ++b) {
                 int dc[3], bt;
-                offset_target(g, b, t, dc, &bt);
+                if (g.lattice == PYHEA_FCC) {
+                    offset_target(g, b, t, dc, &bt);
+                } else {
+                    // BCC site (2X + e, b & 1) of four-site cell X, e = b >> 1
+                    const int e = b >> 1;
+                    int dcb[3], btb;
+                    offset_target(g, b & 1, t, dcb, &btb);
+                    const int x = e + dcb[0];
+                    const int X = x >= 0 ? x / 2 : -((1 - x) / 2);
+                    dc[0] = X;
+                    dc[1] = dcb[1];
+                    dc[2] = dcb[2];
+                    bt = 2 * (x - 2 * X) + btb;
+                }
+                // the layout covers cell deltas of -1..1 along x and y, 0..1 along z
+                if (dc[0] < -1 || dc[0] > 1 || dc[1] < -1 || dc[1] > 1 || dc[2] < 0 || dc[2] > 1) return false;
                 // plane word of the neighbour: layer +dz, sublattice bt, bit shift s
                 const int s = dc[1] * bd->RS + dc[0];
                 const int q = s >= 0 ? s / 32 : -((-s + 31) / 32);

@@ -88,6 +88,9 @@ BATCH_SHAPES = [
     (orc.FCC, (40, 40, 40), 4, 2, 3), (orc.FCC, (33, 5, 7), 3, 4, 4), (orc.FCC, (1, 2, 3), 2, 1, 5),
     (orc.FCC, (70, 3, 6), 6, 2, 4), (orc.FCC, (2, 2, 2), 8, 2, 6), (orc.FCC, (7, 3, 2), 7, 1, 5),
     (orc.FCC, (6, 5, 4), 6, 4, 5), (orc.FCC, (64, 64, 64), 5, 3, 3),
+    # BCC with even Lx runs on the four-site-cell layout; odd Lx and shell 4 use gathers
+    (orc.BCC, (8, 8, 8), 5, 3, 20), (orc.BCC, (2, 3, 3), 3, 3, 7), (orc.BCC, (10, 4, 6), 6, 2, 9),
+    (orc.BCC, (64, 32, 32), 4, 2, 3), (orc.BCC, (7, 4, 4), 3, 2, 5), (orc.BCC, (4, 4, 4), 4, 4, 4),
 ]
 
 
