@@ -374,10 +374,11 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         ChainDesc *hd = (ChainDesc *)hy_at(o_descs);
         int at = 0;
         for (auto &kv : groups) {
-            // longest chains first so the tail of the launch is short
+            // longest chains first (trials x offsets gathered per trial) so the tail
+            // of the launch is short
             std::vector<int> idx = kv.second;
             std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-                return jobs[a].params.n_trials > jobs[b].params.n_trials;
+                return jobs[a].params.n_trials * jobs[a].g.Z > jobs[b].params.n_trials * jobs[b].g.Z;
             });
             Launch L{at,
                      (int)idx.size(),
@@ -396,10 +397,18 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
             }
             launches.push_back(L);
         }
-        // the launch with the most work first, so it starts first
-        std::stable_sort(launches.begin(), launches.end(), [&](const Launch &a, const Launch &b) {
-            return a.count > b.count;
-        });
+        // the launch with the longest chain first, so it starts first (per-trial cost
+        // taken as offsets gathered plus count entries evaluated)
+        auto longest = [&](const Launch &L) {
+            int64_t w = 0;
+            for (int i = L.first; i < L.first + L.count; ++i) {
+                const ChainDesc &d = hd[i];
+                w = std::max<int64_t>(w, d.n_trials * (int64_t)(d.zstart[d.S] + d.M * d.M));
+            }
+            return w;
+        };
+        std::stable_sort(launches.begin(), launches.end(),
+                         [&](const Launch &a, const Launch &b) { return longest(a) > longest(b); });
     }
     uint32_t n_tiles = 0;
     {
