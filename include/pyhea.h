@@ -308,15 +308,16 @@ pyhea_status pyhea_random_configs(int64_t N, int32_t M, const int64_t *compositi
 pyhea_status pyhea_philox4x32_10(const uint32_t *ctr_dev, uint64_t seed, int64_t n,
                                  uint32_t *out_dev, void *stream);
 
-/* Launch shape of the MC kernels.  The library picks it by rule from the
- * chain's size and the number of chains launched together: where the
- * configuration lives (LDS bytes when they fit, else LDS nibbles, else HBM),
- * one wavefront per shell, and the steps per pass.  This switch forces one
- * shape family process-wide: -1 = automatic, 0 = automatic, 1 = LDS nibbles
- * (else HBM), 2 = HBM, 3 = automatic, 4 = offsets spread evenly over the
- * shell wavefronts, 5 = DISJOINT commits decided one by one, 6 = speculative
- * commit chunks of 4 candidates.  Shapes never change results; EINVAL outside
- * -1..6. */
+/* Launch shape of the MC kernels.  The library picks it from the chain's
+ * size and the number of chains launched together: of the stores (LDS bytes,
+ * LDS nibbles, HBM), steps per pass and speculative commit chunks that fit the
+ * LDS, the combination with the best measured rate, one wavefront per shell,
+ * and a block small enough that every chain of the call can be resident.
+ * This switch forces one shape family process-wide: -1 = automatic, 0 =
+ * automatic, 1 = LDS nibbles or HBM, 2 = HBM, 3 = automatic, 4 = offsets
+ * spread evenly over the shell wavefronts, 5 = DISJOINT commits decided one by
+ * one, 6 = speculative commit chunks of 4 candidates.  Shapes never change
+ * results; EINVAL outside -1..6. */
 pyhea_status pyhea_tune_force(int32_t variant);
 
 /* Full-evaluation kernel: -1 = automatic (bit-sliced where it covers the
@@ -330,8 +331,9 @@ pyhea_status pyhea_tune_force_eval(int32_t kernel);
 /* Steps whose candidates one pass of the MC kernel evaluates at once: 0 =
  * automatic (the largest value up to 8 whose block still lets every chain of
  * the call, or every slot of a server, be resident on the GPU at once), or
- * 1..8 (capped so that a block has at most 16 wavefronts).  Candidates are drawn from counters, not from the state, so the
- * candidates of later steps can be evaluated against the current state; a
+ * 1..8 (capped so that a block has at most 16 wavefronts).  Candidates are
+ * drawn from counters, not from the state, so the candidates of later steps
+ * can be evaluated against the current state; a
  * step's evaluation is used only if every earlier step of the pass committed
  * nothing (the state is then unchanged).  Trajectories are bit-identical for
  * every value.  Process-wide; EINVAL outside 0..8. */
