@@ -177,6 +177,40 @@ __device__ __forceinline__ void lds_planes(const uint32_t *p, uint32_t *v) {
     }
 }
 
+// Centre planes of one word: P dwords at p masked to the centre sites cm, their
+// species totals added to this lane's slots, and Un = P_i | P_j at q(i, j), i < j.
+template <int M>
+__device__ __forceinline__ void centre_word(const uint32_t *p, uint32_t cm, int32_t *slots, uint32_t *Pv,
+                                            uint32_t *Un) {
+    constexpr int P = Pairs<M>::P;
+    lds_planes<P>(p, Pv);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        Pv[i] &= cm;
+        // species totals go straight to this lane's slots (no registers held)
+        atomicAdd(slots + i * 64, (int32_t)__popc(Pv[i]));
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+#pragma unroll
+        for (int j = i + 1; j < P; ++j) Un[Pairs<M>::q(i, j)] = Pv[i] | Pv[j];
+}
+
+// One half offset: D_i = popc(P_i & Q_i) and U_ij = popc((P_i | P_j) & (Q_i | Q_j))
+// added to the sums a of its shell; Q are the neighbour planes.
+template <int M>
+__device__ __forceinline__ void count_offset(int32_t *a, const uint32_t *Pv, const uint32_t *Un, const uint32_t *Q) {
+    constexpr int P = Pairs<M>::P;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        a[Pairs<M>::q(i, i)] += __popc(Pv[i] & Q[i]);
+#pragma unroll
+        for (int j = i + 1; j < P; ++j)
+            // (P_i | P_j) & (Q_i | Q_j): one three-input op (0xE0 = a & (b | c))
+            a[Pairs<M>::q(i, j)] += __popc(__builtin_amdgcn_bitop3_b32(Un[Pairs<M>::q(i, j)], Q[i], Q[j], 0xE0));
+    }
+}
+
 // MaxW: the wavefronts per SIMD the register allocation aims for -- 4 for a
 // workgroup alone on its CU (registers spent on overlapping loads), 8 when
 // several workgroups share the CU.
@@ -254,40 +288,46 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
 #pragma unroll
                 for (int j = 0; j < P; ++j) acc[j][g] = 0;
             if constexpr (V4) {
-                // rows of whole 16-byte blocks: block t of the window is block
-                // 8 cxc - 1 + t (mod Lx / 4) of the row, and padded column pos of
-                // the chunk (cell 32 cxc + pos - 1) is word (pos + 3) & 3 of window
-                // block (pos + 3) >> 2.  Two halves of 16 columns, five blocks each
-                // (the last block of the first half is the first of the second).
+                // rows of whole 16-byte blocks: window block t (0..8) of the chunk is
+                // block 8 cxc - 1 + t (mod Lx / 4) of the row, and padded column q of
+                // the chunk (cell 32 cxc + q - 1) is word (q + 3) & 3 of window block
+                // (q + 3) >> 2.  Only the chunk's ncol padded columns are converted
+                // (blocks past the row end wrap to its start: always in bounds).
                 const int nb = bd.Lx >> 2;
-                uint4 blk[5];
+                const int ncol = min(32, RS - 32 * cxc);   // uniform, >= 1
+                // with 4 wavefronts per SIMD every block of the chunk is in flight at
+                // once; with 8, the second half's blocks are read after the first
+                // half's columns (bounds the registers held by loads in flight)
+                constexpr int kFirst = MaxW <= 4 ? 9 : 5;
+                uint4 blk[9];
+                auto load_blk = [&](int t) {
+                    int k = 8 * cxc - 1 + t;
+                    k = k < 0 ? k + nb : k;
+                    while (k >= nb) k -= nb;
+                    blk[t] = *reinterpret_cast<const uint4 *>(cfg + (rowoff + 16u * (uint32_t)k));
+                };
 #pragma unroll
-                for (int half = 0; half < 2; ++half) {
-                    if (32 * cxc + 16 * half >= RS) break;   // uniform
-                    // keep the second half's loads after the first half's use of
-                    // its blocks (bounds the registers held by loads in flight)
-                    __builtin_amdgcn_sched_barrier(0);
-                    if (half == 1) blk[0] = blk[4];
+                for (int t = 0; t < kFirst; ++t) load_blk(t);
 #pragma unroll
-                    for (int t = half; t < 5; ++t) {
-                        int k = 8 * cxc - 1 + 4 * half + t;
-                        k = k < 0 ? k + nb : k;
-                        while (k >= nb) k -= nb;
-                        blk[t] = *reinterpret_cast<const uint4 *>(cfg + (rowoff + 16u * (uint32_t)k));
-                    }
+                for (int q = 0; q < 32; ++q) {
+                    if (kFirst < 9 && q == 16) {
+                        __builtin_amdgcn_sched_barrier(0);
+                        if (ncol > 16) {   // uniform
 #pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        const int t = (q + 3) >> 2, w = (q + 3) & 3;
-                        const uint32_t d = w == 0 ? blk[t].x : w == 1 ? blk[t].y : w == 2 ? blk[t].z : blk[t].w;
-                        const int g = 2 * half + (q >> 3), m = q & 7;
-                        badacc |= d | (d + kBad);
-#pragma unroll
-                        for (int j = 0; j < P; ++j) {
-                            const uint64_t lut = 1ull << (8 * j);
-                            acc[j][g] |= perm((uint32_t)(lut >> 32), (uint32_t)lut, d) << m;
+                            for (int t = kFirst; t < 9; ++t) load_blk(t);
                         }
-                        if (q & 1) __builtin_amdgcn_sched_barrier(0);   // two columns at a time
                     }
+                    if (q >= ncol) continue;   // uniform
+                    const int t = (q + 3) >> 2, w = (q + 3) & 3;
+                    const uint32_t d = w == 0 ? blk[t].x : w == 1 ? blk[t].y : w == 2 ? blk[t].z : blk[t].w;
+                    const int g = q >> 3, m = q & 7;
+                    badacc |= d | (d + kBad);
+#pragma unroll
+                    for (int j = 0; j < P; ++j) {
+                        const uint64_t lut = 1ull << (8 * j);
+                        acc[j][g] |= perm((uint32_t)(lut >> 32), (uint32_t)lut, d) << m;
+                    }
+                    if (q & 1) __builtin_amdgcn_sched_barrier(0);   // two columns at a time
                 }
             } else {
             // padded column pos holds cell (pos - 1) mod Lx; columns past the row
@@ -331,20 +371,35 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
             uint32_t *row0 = lds + (ll * 4 * PW + bd.PADW + wd) * P;
             const int nvalid = RS - 32 * cxc;   // padded columns in this chunk
             const uint32_t keep = nvalid >= 32 ? 0xFFFFFFFFu : (1u << nvalid) - 1u;
+            uint32_t R[P][4];
 #pragma unroll
             for (int j = 0; j < P; ++j) {
                 const uint32_t u0 = perm(acc[j][1], acc[j][0], 0x05010400u);
                 const uint32_t u1 = perm(acc[j][1], acc[j][0], 0x07030602u);
                 const uint32_t v0 = perm(acc[j][3], acc[j][2], 0x05010400u);
                 const uint32_t v1 = perm(acc[j][3], acc[j][2], 0x07030602u);
-                const uint32_t R[4] = {perm(v0, u0, 0x05040100u), perm(v0, u0, 0x07060302u),
-                                       perm(v1, u1, 0x05040100u), perm(v1, u1, 0x07060302u)};
+                R[j][0] = perm(v0, u0, 0x05040100u) & keep;
+                R[j][1] = perm(v0, u0, 0x07060302u) & keep;
+                R[j][2] = perm(v1, u1, 0x05040100u) & keep;
+                R[j][3] = perm(v1, u1, 0x07060302u) & keep;
+            }
+            // planes j and j + 1 of a word are adjacent dwords (8-byte aligned for
+            // even j when P is even): one 64-bit OR for both
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const uint32_t r = R[b] & keep;
-                    uint32_t *dst = row0 + b * PW * P + j;
-                    atomicOr(dst, r << s);
-                    atomicOr(dst + P, (r >> 1) >> (31 - s));
+            for (int b = 0; b < 4; ++b) {
+                uint32_t *dst = row0 + b * PW * P;
+#pragma unroll
+                for (int j = 0; j < P; j += (P % 2 == 0 ? 2 : 1)) {
+                    if constexpr (P % 2 == 0) {
+                        const uint64_t lo = ((uint64_t)(R[j + 1][b] << s) << 32) | (R[j][b] << s);
+                        const uint64_t hi = ((uint64_t)((R[j + 1][b] >> 1) >> (31 - s)) << 32) |
+                                            ((R[j][b] >> 1) >> (31 - s));
+                        atomicOr(reinterpret_cast<unsigned long long *>(dst + j), (unsigned long long)lo);
+                        atomicOr(reinterpret_cast<unsigned long long *>(dst + P + j), (unsigned long long)hi);
+                    } else {
+                        atomicOr(dst + j, R[j][b] << s);
+                        atomicOr(dst + P + j, (R[j][b] >> 1) >> (31 - s));
+                    }
                 }
             }
         }
@@ -358,49 +413,70 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
 #pragma unroll
         for (int q = 0; q < NP; ++q) acc[k][q] = 0;
     const int lane = threadIdx.x & 63;
-    const int nwork = nz * 4 * bd.NCW;
+    int32_t *slots = red2 + S * NP * 64 + lane;   // this lane's species-total slots
+    // Basis-major order with each basis's words padded to whole wavefronts makes
+    // the basis uniform per wavefront: its offset table then comes through scalar
+    // loads, and offsets with no bit shift skip the funnel shift.  Taken when the
+    // padding adds at most a tenth of the words; otherwise words in layer-major
+    // order, each lane reading its basis's table from LDS.
+    const int nbw = nz * bd.NCW;                 // centre words per basis
+    const int nbw64 = (nbw + 63) & ~63;
     const double inv_ncw = 1.0 / bd.NCW;
+    if (10 * nbw64 <= 11 * nbw) {
+        const int nwork = 4 * nbw64;
+        const double inv_nbw = 1.0 / nbw64;
 #pragma unroll 1
-    for (int it = threadIdx.x; it < nwork; it += blockDim.x) {
-        const int lb = qdiv(it, inv_ncw);      // layer * 4 + basis
-        const int w = bd.cw0 + it - lb * bd.NCW;
-        const int b = lb & 3;
-        const int ll = lb >> 2;
-        const uint32_t cm = cmask[w];
-        const uint32_t *lbase = lds + (ll * 4 * PW + bd.PADW + w) * P;
-        uint32_t Pv[P];
-        lds_planes<P>(lbase + b * PW * P, Pv);
+        for (int it = threadIdx.x; it < nwork; it += blockDim.x) {
+            const int bu = __builtin_amdgcn_readfirstlane(qdiv(it, inv_nbw));
+            const int rem = it - bu * nbw64;
+            if (rem >= nbw) continue;   // padding
+            const int ll = qdiv(rem, inv_ncw);
+            const int w = bd.cw0 + rem - ll * bd.NCW;
+            const uint32_t *lbase = lds + (ll * 4 * PW + bd.PADW + w) * P;
+            uint32_t Pv[P], Un[NP];
+            centre_word<M>(lbase + bu * PW * P, cmask[w], slots, Pv, Un);
 #pragma unroll
-        for (int i = 0; i < P; ++i) {
-            Pv[i] &= cm;
-            // species totals go straight to this lane's slots (no registers held)
-            atomicAdd(&red2[(S * NP + i) * 64 + lane], (int32_t)__popc(Pv[i]));
+            for (int k = 0; k < S; ++k) {
+#pragma unroll 1
+                for (int h = bd.hstart[k]; h < bd.hstart[k + 1]; ++h) {
+                    const int r = bd.tab_r[bu][h];
+                    const uint32_t *nb = lbase + bd.tab_delta[bu][h];
+                    uint32_t Q[P];
+                    lds_planes<P>(nb, Q);
+                    if (r != 0) {
+                        uint32_t hi[P];
+                        lds_planes<P>(nb + P, hi);
+#pragma unroll
+                        for (int j = 0; j < P; ++j) Q[j] = __builtin_amdgcn_alignbit(hi[j], Q[j], (uint32_t)r);
+                    }
+                    count_offset<M>(acc[k], Pv, Un, Q);
+                }
+            }
         }
-        uint32_t Un[NP];   // P_i | P_j at q(i, j), i < j
-#pragma unroll
-        for (int i = 0; i < P; ++i)
-#pragma unroll
-            for (int j = i + 1; j < P; ++j) Un[Pairs<M>::q(i, j)] = Pv[i] | Pv[j];
-        const int32_t *tb = tab + 2 * b * bd.nh;
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
+    } else {
+        const int nwork = nz * 4 * bd.NCW;
 #pragma unroll 1
-            for (int h = bd.hstart[k]; h < bd.hstart[k + 1]; ++h) {
-                const uint32_t *nb = lbase + tb[2 * h];
-                const uint32_t r = (uint32_t)tb[2 * h + 1];
-                uint32_t lo[P], hi[P], Q[P];
-                lds_planes<P>(nb, lo);
-                lds_planes<P>(nb + P, hi);
+        for (int it = threadIdx.x; it < nwork; it += blockDim.x) {
+            const int lb = qdiv(it, inv_ncw);      // layer * 4 + basis
+            const int w = bd.cw0 + it - lb * bd.NCW;
+            const int b = lb & 3;
+            const int ll = lb >> 2;
+            const uint32_t *lbase = lds + (ll * 4 * PW + bd.PADW + w) * P;
+            uint32_t Pv[P], Un[NP];
+            centre_word<M>(lbase + b * PW * P, cmask[w], slots, Pv, Un);
+            const int32_t *tb = tab + 2 * b * bd.nh;
 #pragma unroll
-                for (int j = 0; j < P; ++j) Q[j] = __builtin_amdgcn_alignbit(hi[j], lo[j], r);
+            for (int k = 0; k < S; ++k) {
+#pragma unroll 1
+                for (int h = bd.hstart[k]; h < bd.hstart[k + 1]; ++h) {
+                    const uint32_t *nb = lbase + tb[2 * h];
+                    const uint32_t r = (uint32_t)tb[2 * h + 1];
+                    uint32_t lo[P], hi[P], Q[P];
+                    lds_planes<P>(nb, lo);
+                    lds_planes<P>(nb + P, hi);
 #pragma unroll
-                for (int i = 0; i < P; ++i) {
-                    acc[k][Pairs<M>::q(i, i)] += __popc(Pv[i] & Q[i]);
-#pragma unroll
-                    for (int j = i + 1; j < P; ++j)
-                        // (P_i | P_j) & (Q_i | Q_j): one three-input op (0xE0 = a & (b | c))
-                        acc[k][Pairs<M>::q(i, j)] +=
-                            __popc(__builtin_amdgcn_bitop3_b32(Un[Pairs<M>::q(i, j)], Q[i], Q[j], 0xE0));
+                    for (int j = 0; j < P; ++j) Q[j] = __builtin_amdgcn_alignbit(hi[j], lo[j], r);
+                    count_offset<M>(acc[k], Pv, Un, Q);
                 }
             }
         }
