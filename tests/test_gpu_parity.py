@@ -91,6 +91,11 @@ BATCH_SHAPES = [
     # BCC with even Lx runs on the four-site-cell layout; odd Lx and shell 4 use gathers
     (orc.BCC, (8, 8, 8), 5, 3, 20), (orc.BCC, (2, 3, 3), 3, 3, 7), (orc.BCC, (10, 4, 6), 6, 2, 9),
     (orc.BCC, (64, 32, 32), 4, 2, 3), (orc.BCC, (7, 4, 4), 3, 2, 5), (orc.BCC, (4, 4, 4), 4, 4, 4),
+    # counting order: a two-layer workgroup with 60-64 centre words per basis walks
+    # them basis-major (padded to one wavefront), a one-layer workgroup layer-major;
+    # the first three launches hold one of each
+    (orc.FCC, (12, 66, 3), 5, 3, 3), (orc.FCC, (13, 61, 3), 4, 2, 3), (orc.BCC, (24, 66, 3), 6, 2, 3),
+    (orc.FCC, (12, 67, 2), 8, 1, 3), (orc.FCC, (12, 66, 2), 3, 4, 3),
 ]
 
 
@@ -122,6 +127,37 @@ def _batch_case(lattice, L, M, S, K):
         if k in (1, 2) or (np.bincount(cfg[k], minlength=M) == 0).any():
             assert np.all(np.isnan(sf[k]))
             continue
+        want = orc.counts(lattice, L, M, S, cfg[k])
+        np.testing.assert_array_equal(c[k], want)
+        _, _, S_o, F_o = orc.alpha_objective(lattice, L, M, S, cfg[k], want, tgt, w)
+        assert sf[k, 0] == S_o and sf[k, 1] == F_o
+
+
+def test_sro_eval_batch_whole_configurations_per_workgroup():
+    """260 configurations of FCC 20^3 (5 species, shells 1-3): one workgroup per
+    configuration holding all 20 layers, words walked basis-major (300 per basis,
+    padded to 320) as in the 32,768-configuration batch; every 13th configuration
+    is checked against the oracle, all of them against the row sums
+    sum_j N_ij = z_k n_i."""
+    lattice, L, M, S, K = orc.FCC, (20, 20, 20), 5, 3, 260
+    N = orc.n_sites(lattice, L)
+    cfg = wl.iid_configs(N, M, K, seed=11)
+    rng = np.random.default_rng(2)
+    tgt = rng.uniform(-0.2, 0.2, (S, M, M))
+    w = rng.uniform(0.1, 1.0, S)
+    counts = torch.zeros((K, S, M, M), dtype=torch.int32, device="cuda")
+    SF = torch.zeros((K, 2), dtype=torch.float64, device="cuda")
+    pb.pyhea_sro_eval_batch(lattice, L, M, S, dev(cfg), counts, tgt, w, SF)
+    torch.cuda.synchronize()
+    c = counts.cpu().numpy()
+    sf = SF.cpu().numpy()
+    z = [12, 6, 24]
+    for k in range(K):
+        n = np.bincount(cfg[k], minlength=M)
+        for s in range(S):
+            np.testing.assert_array_equal(c[k, s].sum(axis=1), z[s] * n)
+            np.testing.assert_array_equal(c[k, s], c[k, s].T)
+    for k in range(0, K, 13):
         want = orc.counts(lattice, L, M, S, cfg[k])
         np.testing.assert_array_equal(c[k], want)
         _, _, S_o, F_o = orc.alpha_objective(lattice, L, M, S, cfg[k], want, tgt, w)
