@@ -143,6 +143,8 @@ const char *pyhea_last_error(void);
  *   counts_host  [S][M][M] int64 (may be NULL).
  *   alpha_host   [S][M][M] double (may be NULL).
  *   S_F_host     [2] = {S, F} (ignored when obj is NULL).
+ * Counts, alpha, S and F are computed on the device (one counting launch and
+ * one objective launch on `stream`), then read back in one copy.
  * Synchronous.  PYHEA_EINVAL if a species id is outside [0, M) or some
  * species is absent (c_j = 0 leaves Eq. 2 undefined).
  */

@@ -63,34 +63,48 @@ pyhea_status pyhea_sro_eval(const pyhea_lattice *lat, const int8_t *species_dev,
     }
     hipStream_t stream = as_stream(stream_);
     const int E = g.S * g.M * g.M;
+    // device block: counts [E] | bad | alpha [E] | S, F | target [E], weight [S]
+    const size_t o_bad = ((size_t)E * 4 + 7) & ~size_t(7);
+    const size_t o_alpha = o_bad + 8;
+    const size_t o_sf = o_alpha + (size_t)E * 8;
+    const size_t o_tw = o_sf + 16;
     AsyncBuffer buf;
     buf.stream = stream;
-    PYHEA_HIP(pool_alloc(&buf.ptr, E * 4 + 256, stream));
-    int32_t *counts = (int32_t *)buf.ptr;
-    int32_t *bad = (int32_t *)((char *)buf.ptr + ((E * 4 + 127) & ~127));
+    PYHEA_HIP(pool_alloc(&buf.ptr, o_tw + (size_t)(E + kMaxShells) * 8, stream));
+    char *base = (char *)buf.ptr;
+    int32_t *counts = (int32_t *)base;
+    int32_t *bad = (int32_t *)(base + o_bad);
+    double *tdev = (double *)(base + o_tw);
     {
         const pyhea_status s = count_configs(g, 1, species_dev, counts, bad, stream);
         if (s != PYHEA_OK) return s;
     }
-    std::vector<int32_t> c32(E);
-    int32_t badh = 0;
-    PYHEA_HIP(hipMemcpyAsync(c32.data(), counts, E * 4, hipMemcpyDeviceToHost, stream));
-    PYHEA_HIP(hipMemcpyAsync(&badh, bad, 4, hipMemcpyDeviceToHost, stream));
+    if (obj) {
+        SmallTable tw{};
+        std::memcpy(tw.v, obj->target, E * 8);
+        std::memcpy(tw.v + E, obj->weight, g.S * 8);
+        PYHEA_HIP(launch_upload(tw, E + kMaxShells, tdev, stream));
+    }
+    // alpha, S and F (Eq. 2-3) on the device, then one read-back
+    EvalDesc ed;
+    fill_eval_desc(g, &ed);
+    PYHEA_HIP(launch_objective_epilogue(ed, 1, counts, bad, obj ? tdev : nullptr, obj ? tdev + E : nullptr,
+                                        (double *)(base + o_sf), (double *)(base + o_alpha), stream));
+    std::vector<char> h(o_tw);
+    PYHEA_HIP(hipMemcpyAsync(h.data(), base, o_tw, hipMemcpyDeviceToHost, stream));
     PYHEA_HIP(hipStreamSynchronize(stream));
-    std::vector<int64_t> c64(c32.begin(), c32.end());
+    const int32_t *c32 = (const int32_t *)h.data();
+    int32_t badh;
+    std::memcpy(&badh, h.data() + o_bad, 4);
+    std::vector<int64_t> c64(c32, c32 + E);
     int64_t n[kMaxSpecies];
     if (badh || !species_totals(g, c64.data(), n)) {
         set_error("species ids must lie in [0, n_species) and every species must occur");
         return PYHEA_EINVAL;
     }
     if (counts_host) std::memcpy(counts_host, c64.data(), E * 8);
-    double SF[2];
-    host_objective(g, c64.data(), obj ? obj->target : nullptr, obj ? obj->weight : nullptr, alpha_host,
-                   SF);
-    if (obj && S_F_host) {
-        S_F_host[0] = SF[0];
-        S_F_host[1] = SF[1];
-    }
+    if (alpha_host) std::memcpy(alpha_host, h.data() + o_alpha, E * 8);
+    if (obj && S_F_host) std::memcpy(S_F_host, h.data() + o_sf, 16);
     return guard(PYHEA_OK);
 }
 
@@ -140,7 +154,7 @@ pyhea_status pyhea_sro_eval_batch(const pyhea_lattice *lat, int64_t n_configs, c
         if (s != PYHEA_OK) return s;
     }
     if (obj && !fused)
-        PYHEA_HIP(launch_objective_epilogue(ed, n_configs, counts_dev, bad, tdev, tdev + E, S_F_dev, stream));
+        PYHEA_HIP(launch_objective_epilogue(ed, n_configs, counts_dev, bad, tdev, tdev + E, S_F_dev, nullptr, stream));
     return guard(PYHEA_OK);
 }
 

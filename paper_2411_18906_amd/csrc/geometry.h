@@ -70,6 +70,7 @@ struct ChainState {
     int32_t stop_reason;
     int32_t done;
     int32_t status;
+    double S, F;   // objective of the final counts (Eq. 3), written after the run
 };
 
 enum SpeciesStore : int32_t {

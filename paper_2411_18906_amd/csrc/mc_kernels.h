@@ -52,6 +52,8 @@ hipError_t launch_pad_fill(const ChainDesc *descs_dev, int n_chains, hipStream_t
 hipError_t launch_pad_drain(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);
 // out[i] = *descs_dev[i].state (device array of n_chains states).
 hipError_t launch_gather_states(const ChainDesc *descs_dev, int n_chains, ChainState *out, hipStream_t stream);
+// S and F of every chain's maintained counts into its state (Eq. 2-3).
+hipError_t launch_final_objective(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);
 
 // Full evaluation: pair counts of K configurations of one geometry.
 struct EvalDesc {
@@ -96,9 +98,10 @@ hipError_t launch_upload(const SmallTable &t, int n, double *dst, hipStream_t st
 
 hipError_t launch_count_gather(const EvalDesc &ed, int64_t K, const int8_t *species,
                                int32_t *counts, int32_t *bad, hipStream_t stream);
+// alpha (optional, [K][S][M][M]) and, with a target, S_F [K][2] from counts.
 hipError_t launch_objective_epilogue(const EvalDesc &ed, int64_t K, const int32_t *counts,
                                      const int32_t *bad, const double *target, const double *weight,
-                                     double *S_F, hipStream_t stream);
+                                     double *S_F, double *alpha, hipStream_t stream);
 hipError_t launch_trial_eval(const EvalDesc &ed, const int8_t *species, const int32_t *counts,
                              const double *target, const double *weight, int64_t n_pairs,
                              const int32_t *pairs, double *dS, int32_t *dN, hipStream_t stream);

@@ -135,36 +135,6 @@ void ratio_table(const Geometry &g, const int64_t *n, double *R) {
                 R[(k * g.M + i) * g.M + j] = (double)g.N / (double)(n[i] * n[j] * (int64_t)g.z[k]);
 }
 
-void host_objective(const Geometry &g, const int64_t *counts, const double *target,
-                    const double *weight, double *alpha, double *S_F) {
-    int64_t n[kMaxSpecies];
-    species_totals(g, counts, n);
-    std::vector<double> R(g.S * g.M * g.M);
-    ratio_table(g, n, R.data());
-    double sum = 0.0;
-    for (int k = 0; k < g.S; ++k) {
-        double Q = 0.0;
-        for (int i = 0; i < g.M; ++i) {
-            double row = 0.0;
-            for (int j = 0; j < g.M; ++j) {
-                const int e = (k * g.M + i) * g.M + j;
-                const double a = 1.0 - (double)counts[e] * R[e];
-                if (alpha) alpha[e] = a;
-                if (target) {
-                    const double d = a - target[e];
-                    row = row + d * d;
-                }
-            }
-            Q = Q + row;
-        }
-        if (weight) sum = sum + weight[k] * Q;
-    }
-    if (S_F) {
-        S_F[0] = sum;
-        S_F[1] = std::sqrt(sum);
-    }
-}
-
 pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, int32_t *counts,
                            int32_t *bad, hipStream_t stream, const double *tw, double *S_F, bool *fused) {
     if (fused) *fused = false;
@@ -469,7 +439,9 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         PYHEA_HIP(fork.end());
     }
 
-    // results: states, maintained counts, and a fresh recount of every final configuration
+    // results: states with the final objective, maintained counts, and a fresh
+    // recount of every final configuration
+    PYHEA_HIP(launch_final_objective(ddev, n, stream));
     PYHEA_HIP(launch_count_tasks(tasks + n, tile0, n, n_tiles, stream));
     PYHEA_HIP(hipMemcpyAsync(hx.data(), base, x_end, hipMemcpyDeviceToHost, stream));
     PYHEA_HIP(hipStreamSynchronize(stream));
@@ -478,7 +450,6 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
     const ChainState *sts = (const ChainState *)(hx.data() + o_state);
     if (final_counts) final_counts->assign(n, {});
     for (int c = 0; c < n; ++c) {
-        const Geometry &g = jobs[c].g;
         if (!std::equal(cnt + eoff[c], cnt + eoff[c + 1], rec + eoff[c])) {
             set_error("chain " + std::to_string(c) + ": maintained pair counts differ from a recount");
             return PYHEA_EDEVICE;
@@ -492,10 +463,8 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         s.steps = sts[c].steps;
         s.stop_reason = sts[c].stop_reason;
         s.status = PYHEA_OK;
-        double SF[2];
-        host_objective(g, c64.data(), jobs[c].target.data(), jobs[c].weight.data(), nullptr, SF);
-        s.S = SF[0];
-        s.F = SF[1];
+        s.S = sts[c].S;
+        s.F = sts[c].F;
         s.log_len = jobs[c].log_dev ? std::min(s.commits, jobs[c].log_cap) : 0;
         if (final_counts) (*final_counts)[c] = c64;
     }

@@ -35,12 +35,12 @@ pyhea_status check_objective(const Geometry &g, const pyhea_objective *obj);
 // Checks MC parameters.
 pyhea_status check_params(const pyhea_mc_params *p);
 
-// Host evaluation of Eq. 2-3 from exact counts (int64 [S][M][M]).
-// n[i] = row sum of shell 1 / z_1.  Returns false if some n_i == 0.
+// Species totals from exact counts (int64 [S][M][M]): n[i] = row sum of shell 1
+// / z_1.  Returns false if some n_i == 0 (input validation).
 bool species_totals(const Geometry &g, const int64_t *counts, int64_t *n);
+// R[k][i][j] = N / (n_i n_j z_k): one exact int64 product and one IEEE division
+// per entry, the table the kernels read (Eq. 2).
 void ratio_table(const Geometry &g, const int64_t *n, double *R);
-void host_objective(const Geometry &g, const int64_t *counts, const double *target,
-                    const double *weight, double *alpha, double *S_F);
 
 // One chain prepared for the MC kernel.
 struct ChainJob {

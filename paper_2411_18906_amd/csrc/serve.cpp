@@ -244,6 +244,12 @@ void Server::retire(const std::vector<Job *> &js, hipStream_t s) {
         ok = ok && launch_pad_drain((const ChainDesc *)aux_desc_dev, (int)pads.size(), s) == hipSuccess;
     }
     ok = ok && count_jobs(js, true, task_dev, s);
+    // S and F of the final counts into each job's state
+    std::vector<ChainDesc> ds;
+    for (Job *j : js) ds.push_back(j->desc);
+    ok = ok && hipMemcpyAsync(aux_desc_dev, ds.data(), ds.size() * sizeof(ChainDesc), hipMemcpyHostToDevice, s) ==
+                   hipSuccess;
+    ok = ok && launch_final_objective((const ChainDesc *)aux_desc_dev, (int)ds.size(), s) == hipSuccess;
     std::vector<std::vector<char>> small(js.size());
     for (size_t i = 0; ok && i < js.size(); ++i) {
         Job *j = js[i];
@@ -265,16 +271,13 @@ void Server::retire(const std::vector<Job *> &js, hipStream_t s) {
         } else {
             ChainState st;
             std::memcpy(&st, small[i].data() + j->lay.state, sizeof(st));
-            std::vector<int64_t> c64(cr, cr + E);
-            double SF[2];
-            host_objective(g, c64.data(), j->target.data(), j->weight.data(), nullptr, SF);
             j->stats.trials = st.trials;
             j->stats.null_trials = st.null_trials;
             j->stats.commits = st.commits;
             j->stats.steps = st.steps;
             j->stats.stop_reason = st.stop_reason;
-            j->stats.S = SF[0];
-            j->stats.F = SF[1];
+            j->stats.S = st.S;
+            j->stats.F = st.F;
         }
         j->stats.status = j->status;
     }

@@ -164,10 +164,12 @@ __global__ void zero_i32_kernel(int32_t *p, int64_t n) {
 
 // alpha / S / F of Eq. 2-3 per configuration (one thread per configuration),
 // binary64, no contraction: R = N / (n_i n_j z_k), alpha = 1 - N_ij R,
-// Q_k = sum_i (sum_j (alpha - t)^2), S = sum_k w_k Q_k, F = sqrt(S).
+// Q_k = sum_i (sum_j (alpha - t)^2), S = sum_k w_k Q_k, F = sqrt(S).  alpha
+// [K][S][M][M] is written when non-null, S_F when target is non-null.
 __global__ void objective_kernel(EvalDesc ed, int64_t K, const int32_t *__restrict__ counts,
                                  const int32_t *__restrict__ bad, const double *__restrict__ target,
-                                 const double *__restrict__ weight, double *__restrict__ S_F) {
+                                 const double *__restrict__ weight, double *__restrict__ S_F,
+                                 double *__restrict__ alpha) {
     const int64_t kc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (kc >= K) return;
     const int M = ed.M, E = ed.S * M * M;
@@ -181,8 +183,10 @@ __global__ void objective_kernel(EvalDesc ed, int64_t K, const int32_t *__restri
         ok = ok && n[i] > 0;
     }
     if (!ok) {
-        S_F[2 * kc] = __longlong_as_double(0x7ff8000000000000ll);
-        S_F[2 * kc + 1] = __longlong_as_double(0x7ff8000000000000ll);
+        if (target) {
+            S_F[2 * kc] = __longlong_as_double(0x7ff8000000000000ll);
+            S_F[2 * kc + 1] = __longlong_as_double(0x7ff8000000000000ll);
+        }
         return;
     }
     double sum = 0.0;
@@ -194,15 +198,20 @@ __global__ void objective_kernel(EvalDesc ed, int64_t K, const int32_t *__restri
                 const int e = (k * M + i) * M + j;
                 const double R = (double)ed.N / (double)(n[i] * n[j] * (int64_t)ed.zk[k]);
                 const double a = 1.0 - (double)c[e] * R;
-                const double dd = a - target[e];
-                row = row + dd * dd;
+                if (alpha) alpha[kc * E + e] = a;
+                if (target) {
+                    const double dd = a - target[e];
+                    row = row + dd * dd;
+                }
             }
             Q = Q + row;
         }
-        sum = sum + weight[k] * Q;
+        if (target) sum = sum + weight[k] * Q;
     }
-    S_F[2 * kc] = sum;
-    S_F[2 * kc + 1] = sqrt(sum);
+    if (target) {
+        S_F[2 * kc] = sum;
+        S_F[2 * kc + 1] = sqrt(sum);
+    }
 }
 
 // site id of position (x, y, z) in half units, wrapped into the box
@@ -342,10 +351,10 @@ hipError_t launch_count_tasks(const CountTask *tasks, const uint32_t *tile0, int
 
 hipError_t launch_objective_epilogue(const EvalDesc &ed, int64_t K, const int32_t *counts,
                                      const int32_t *bad, const double *target, const double *weight,
-                                     double *S_F, hipStream_t stream) {
+                                     double *S_F, double *alpha, hipStream_t stream) {
     const int blocks = (int)((K + 255) / 256);
     hipLaunchKernelGGL(objective_kernel, dim3(blocks), dim3(256), 0, stream, ed, K, counts, bad, target,
-                       weight, S_F);
+                       weight, S_F, alpha);
     return hipGetLastError();
 }
 
