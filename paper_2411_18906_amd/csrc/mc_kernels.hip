@@ -919,33 +919,6 @@ __global__ void gather_states_kernel(const ChainDesc *__restrict__ descs, int n,
     if (i < n) out[i] = *descs[i].state;
 }
 
-// Eq. 2-3 on a chain's maintained counts, binary64 in the host contract's order
-// (alpha = 1 - N R, (alpha - t)^2 summed along a row, rows into Q_k, S = sum_k
-// w_k Q_k), written to its state with F = sqrt(S).  One thread per chain.
-__global__ void final_objective_kernel(const ChainDesc *__restrict__ descs, int n) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    const ChainDesc &d = descs[c];
-    const int M = d.M;
-    double sum = 0.0;
-    for (int k = 0; k < d.S; ++k) {
-        double Q = 0.0;
-        for (int i = 0; i < M; ++i) {
-            double row = 0.0;
-            for (int j = 0; j < M; ++j) {
-                const int e = (k * M + i) * M + j;
-                const double a = 1.0 - (double)d.counts[e] * d.R[e];
-                const double dd = a - d.target[e];
-                row = row + dd * dd;
-            }
-            Q = Q + row;
-        }
-        sum = sum + d.w[k] * Q;
-    }
-    d.state->S = sum;
-    d.state->F = sqrt(sum);
-}
-
 __global__ void pad_fill_kernel(const ChainDesc *__restrict__ descs) {
     const ChainDesc &d = descs[blockIdx.y];
     if (d.store != kStoreGlobal) return;
@@ -998,12 +971,6 @@ hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M,
     if (e != hipSuccess) return e;
     void *args[] = {(void *)&descs_dev, (void *)&max_steps, (void *)&W, (void *)&bal, (void *)&K, (void *)&CH};
     return hipLaunchKernel(fn, grid, block, args, (size_t)lds_bytes, stream);
-}
-
-hipError_t launch_final_objective(const ChainDesc *descs_dev, int n_chains, hipStream_t stream) {
-    if (n_chains <= 0) return hipSuccess;
-    hipLaunchKernelGGL(final_objective_kernel, dim3((n_chains + 63) / 64), dim3(64), 0, stream, descs_dev, n_chains);
-    return hipGetLastError();
 }
 
 hipError_t launch_gather_states(const ChainDesc *descs_dev, int n_chains, ChainState *out, hipStream_t stream) {

@@ -214,6 +214,33 @@ __global__ void objective_kernel(EvalDesc ed, int64_t K, const int32_t *__restri
     }
 }
 
+// Eq. 2-3 on a chain's maintained counts, binary64 in the host contract's order
+// (alpha = 1 - N R, (alpha - t)^2 summed along a row, rows into Q_k, S = sum_k
+// w_k Q_k), written to its state with F = sqrt(S).  One thread per chain.
+__global__ void final_objective_kernel(const ChainDesc *__restrict__ descs, int n) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const ChainDesc &d = descs[c];
+    const int M = d.M;
+    double sum = 0.0;
+    for (int k = 0; k < d.S; ++k) {
+        double Q = 0.0;
+        for (int i = 0; i < M; ++i) {
+            double row = 0.0;
+            for (int j = 0; j < M; ++j) {
+                const int e = (k * M + i) * M + j;
+                const double a = 1.0 - (double)d.counts[e] * d.R[e];
+                const double dd = a - d.target[e];
+                row = row + dd * dd;
+            }
+            Q = Q + row;
+        }
+        sum = sum + d.w[k] * Q;
+    }
+    d.state->S = sum;
+    d.state->F = sqrt(sum);
+}
+
 // site id of position (x, y, z) in half units, wrapped into the box
 __device__ __forceinline__ int32_t site_at(const EvalDesc &ed, int x, int y, int z) {
     x = wrap1(x, 2 * ed.Lx);
@@ -355,6 +382,12 @@ hipError_t launch_objective_epilogue(const EvalDesc &ed, int64_t K, const int32_
     const int blocks = (int)((K + 255) / 256);
     hipLaunchKernelGGL(objective_kernel, dim3(blocks), dim3(256), 0, stream, ed, K, counts, bad, target,
                        weight, S_F, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_final_objective(const ChainDesc *descs_dev, int n_chains, hipStream_t stream) {
+    if (n_chains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(final_objective_kernel, dim3((n_chains + 63) / 64), dim3(64), 0, stream, descs_dev, n_chains);
     return hipGetLastError();
 }
 
