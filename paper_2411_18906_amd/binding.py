@@ -9,6 +9,7 @@ back to anything else.
 from __future__ import annotations
 
 import ctypes
+import itertools
 import os
 
 import numpy as np
@@ -249,12 +250,13 @@ def _batch_descriptors(problems):
     """Lattice array, objective pointer array and the host block they point
     into, for n problems, built with a few numpy calls."""
     n = len(problems)
-    lat = np.array([(p[0], tuple(p[1]), p[2], p[3]) for p in problems], dtype=_LAT_DTYPE)
-    parts = []
-    for p in problems:
-        parts.append(np.asarray(p[4], dtype=np.float64).reshape(-1))
-        parts.append(np.asarray(p[5], dtype=np.float64).reshape(-1))
-    block = np.ascontiguousarray(np.concatenate(parts))
+    lat = np.fromiter(itertools.chain.from_iterable((p[0], *p[1], p[2], p[3]) for p in problems),
+                      dtype=np.int32, count=6 * n).view(_LAT_DTYPE)
+    try:
+        block = np.concatenate([a.ravel() for p in problems for a in (p[4], p[5])]).astype(np.float64, copy=False)
+    except AttributeError:   # targets or weights given as sequences
+        block = np.concatenate([np.asarray(a, dtype=np.float64).ravel() for p in problems for a in (p[4], p[5])])
+    block = np.ascontiguousarray(block)
     S = lat["n_shells"].astype(np.int64)
     E = S * lat["n_species"].astype(np.int64) ** 2
     start = np.concatenate([[0], np.cumsum(E + S)])
@@ -266,6 +268,18 @@ def _batch_descriptors(problems):
     return lat, obj, block
 
 
+_STATS_DTYPE = np.dtype(McStats)
+
+
+def _params_block(params_list):
+    """The McParams array as one host buffer (bytes of each structure)."""
+    if all(type(x) is McParams for x in params_list):
+        raw = b"".join(map(bytes, params_list))
+    else:
+        raw = bytes((McParams * len(params_list))(*params_list))
+    return np.frombuffer(raw, dtype=np.uint8).copy()   # aligned, owned
+
+
 def pyhea_mc_batch(problems, species, offsets, params_list, log=None, log_offsets=None,
                    stream=None):
     """Many chains in one call.  problems: list of (lattice, L, M, S, target,
@@ -274,16 +288,18 @@ def pyhea_mc_batch(problems, species, offsets, params_list, log=None, log_offset
     pyhea_mc_stats: stats[i]["F"], ...)."""
     import torch
     n = len(problems)
+    if len(params_list) != n:
+        raise ValueError("one parameter set per problem")
     lat, obj, block = _batch_descriptors(problems)
-    pars = (McParams * n)(*params_list)
-    stats = (McStats * n)()
+    pars = _params_block(params_list)
+    stats = np.zeros(n, dtype=_STATS_DTYPE)
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
     loff = None if log_offsets is None else np.ascontiguousarray(np.asarray(log_offsets, np.int64))
-    _check(lib().pyhea_mc_batch(n, _hptr(lat), _hptr(obj), pars, _dptr(species, torch.int8), _hptr(off),
+    _check(lib().pyhea_mc_batch(n, _hptr(lat), _hptr(obj), _hptr(pars), _dptr(species, torch.int8), _hptr(off),
                                 _dptr(log, torch.int32) if log is not None else None,
-                                _hptr(loff), stats, _stream(stream)))
+                                _hptr(loff), _hptr(stats), _stream(stream)))
     del block
-    return np.ctypeslib.as_array(stats).copy()
+    return stats
 
 
 def pyhea_philox4x32_10(ctr, seed: int, out, stream=None):
