@@ -64,3 +64,36 @@ def test_host_side_validation_without_gpu(libpath):
         assert L.pyhea_last_error().decode()
     assert L.pyhea_tune_force(99) == b.EINVAL
     assert L.pyhea_tune_force(-1) == b.OK
+
+
+def test_batch_marshalling_matches_per_chain_structures():
+    """The batched-chain binding packs lattices, objective pointers and
+    parameters with numpy; the packed bytes must equal the C structures built
+    one chain at a time (sequence inputs included)."""
+    import numpy as np
+    from paper_2411_18906_amd import binding as pb
+    rng = np.random.default_rng(4)
+    problems, params = [], []
+    for c in range(40):
+        M, S = int(rng.integers(2, 9)), int(rng.integers(1, 5))
+        L = tuple(int(x) for x in rng.integers(1, 30, 3))
+        t = rng.uniform(-0.2, 0.2, (S, M, M))
+        w = rng.uniform(0.1, 1.0, S)
+        if c % 3 == 0:   # plain sequences and other dtypes
+            t, w, L = t.tolist(), w.astype(np.float32), list(L)
+        problems.append((int(rng.integers(0, 2)), L, M, S, t, w))
+        params.append(pb.make_params(int(rng.integers(0, 2**63)), c, int(rng.integers(0, 10**6)),
+                                     int(rng.integers(1, 257)), c % 2, c % 5, 0.25 * (c % 3)))
+    lat, obj, block = pb._batch_descriptors(problems)
+    for i, p in enumerate(problems):
+        ref = pb.make_lattice(p[0], p[1], p[2], p[3])
+        assert lat[i].tobytes() == bytes(ref)
+        S, M = p[3], p[2]
+        t = ctypes.cast(ctypes.c_void_p(int(obj[i, 0])), ctypes.POINTER(ctypes.c_double * (S * M * M))).contents
+        w = ctypes.cast(ctypes.c_void_p(int(obj[i, 1])), ctypes.POINTER(ctypes.c_double * S)).contents
+        np.testing.assert_array_equal(np.array(t), np.asarray(p[4], np.float64).ravel())
+        np.testing.assert_array_equal(np.array(w), np.asarray(p[5], np.float64).ravel())
+    packed = pb._params_block(params)
+    assert packed.tobytes() == bytes((pb.McParams * len(params))(*params))
+    assert pb._STATS_DTYPE.itemsize == ctypes.sizeof(pb.McStats)
+    assert pb._STATS_DTYPE.names == tuple(f for f, _ in pb.McStats._fields_)
