@@ -50,18 +50,6 @@ __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel)
     return __builtin_amdgcn_perm(hi, lo, sel);
 }
 
-// Sum over the 64 lanes of a wave, valid in lane 63: quad swaps, half-row and
-// row mirrors, then row broadcasts 15 and 31 (DPP; no LDS traffic).
-__device__ __forceinline__ int wave_sum(int v) {
-    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
-    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
-    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
-    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31
-    return v;
-}
-
 // floor(n / d) for small non-negative n, d (see div_small)
 __device__ __forceinline__ int qdiv(int n, double inv) { return (int)div_small((uint32_t)n, inv); }
 
@@ -234,7 +222,7 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
     const int RS = bd.RS;
     const int nplane = nl * 4 * PW * P;      // plane dwords (a multiple of 4)
     uint32_t *cmask = lds + nplane;          // centre mask per word [LW]
-    int32_t *red2 = (int32_t *)(cmask + bd.LW);  // per-lane sums [NV][64]
+    int32_t *red2 = (int32_t *)(cmask + ((bd.LW + 3) & ~3));  // per-lane sums [NV][64], 16-byte aligned
     int32_t *red = red2 + NV * 64;               // totals [NV + 1]
     int32_t *tab = red + NV + 1;                 // (delta, shift) per (basis, half offset)
     for (int i = threadIdx.x; i < 4 * bd.nh; i += blockDim.x) {
@@ -481,7 +469,7 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
             }
         }
     }
-    // ---- 3. reduce over the workgroup: per-lane slots, then one wave_sum per value ----
+    // ---- 3. reduce over the workgroup: per-lane slots, then one lane per value ----
     {
 #pragma unroll
         for (int k = 0; k < S; ++k)
@@ -490,10 +478,18 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
         const uint64_t anybad = __ballot((badacc & 0x80808080u) != 0);
         if (lane == 0 && anybad) atomicOr(&red[NV], 1);
         __syncthreads();
-        const int nwaves = blockDim.x >> 6;
-        for (int v = threadIdx.x >> 6; v < NV; v += nwaves) {
-            const int t = wave_sum(red2[v * 64 + lane]);
-            if (lane == 63) red[v] = t;
+        // one lane per value adds its 64 slots (16-byte reads, rotated per lane
+        // so that lanes start on different banks)
+        if (threadIdx.x < NV) {
+            const int v = threadIdx.x;
+            const uint4 *row = reinterpret_cast<const uint4 *>(red2 + v * 64);
+            uint32_t t = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const uint4 x = row[(j + v) & 15];
+                t += x.x + x.y + x.z + x.w;
+            }
+            red[v] = (int32_t)t;
         }
     }
     __syncthreads();
@@ -568,7 +564,7 @@ hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_
                      int32_t *bad, const double *tw, double *S_F, hipStream_t stream) {
     const int P = M - 1;
     const int NV = S * Pairs<M>::NP + P;
-    const size_t lds = ((size_t)(bd.ZC + 1) * 4 * P * bd.PW + bd.LW + NV * 64 + NV + 1 + 8 * bd.nh + 1 +
+    const size_t lds = ((size_t)(bd.ZC + 1) * 4 * P * bd.PW + ((bd.LW + 3) & ~3) + NV * 64 + NV + 1 + 8 * bd.nh + 1 +
                         3 * S * M * M + 2 * S * M + 2) * 4;
     const bool lone = bd.threads > 512;   // one workgroup per CU
     using KernelFn = void (*)(BitDesc, int64_t, const int8_t *, int32_t *, int32_t *, int32_t *, const double *,
@@ -652,7 +648,7 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitD
     for (int k = 0; k < kMaxShells; ++k) bd->zk[k] = k < g.S ? g.z[k] : 0;
     // largest z-chunk whose planes fit in LDS
     const int nv = g.S * np + P;
-    const int fixed = (bd->LW + nv * 64 + nv + 1 + 8 * kMaxOffsets / 2 + 3 * g.S * g.M * g.M + 2 * g.S * g.M + 3) * 4;
+    const int fixed = (((bd->LW + 3) & ~3) + nv * 64 + nv + 1 + 8 * kMaxOffsets / 2 + 3 * g.S * g.M * g.M + 2 * g.S * g.M + 3) * 4;
     const int per_layer = 4 * P * bd->PW * 4;
     // split > 1: a configuration whose layers would take more than 1/split of a
     // CU's LDS is cut along z so that `split` workgroups share each CU
