@@ -266,7 +266,9 @@ pyhea_status pyhea_serve_cancel(void *server, uint64_t job_id);
  * rounds, bytes_resident}. */
 pyhea_status pyhea_serve_counters(void *server, int64_t *out8_host);
 
-/* Stop the worker, drop unfinished jobs and free the server. */
+/* Stop the worker, end unfinished jobs as cancelled (a poll blocked on one
+ * returns PYHEA_EDEVICE; close waits for it to leave) and free the server.
+ * No call may use the handle after close has started. */
 pyhea_status pyhea_serve_close(void *server);
 
 /*

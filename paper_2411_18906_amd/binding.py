@@ -154,6 +154,25 @@ def make_lattice(lattice: int, L, M: int, S: int) -> Lattice:
     return Lattice(lattice, (ctypes.c_int32 * 3)(*[int(x) for x in L]), M, S)
 
 
+def n_sites(lattice: int, L) -> int:
+    """Sites of the supercell (4 per FCC cell, 2 per BCC cell); the library
+    itself rejects a malformed lattice code."""
+    a = 4 if lattice == FCC else 2
+    return a * int(L[0]) * int(L[1]) * int(L[2])
+
+
+def _need(t, numel: int, what: str):
+    """Raise ValueError unless buffer t holds exactly numel elements."""
+    n = int(t.numel()) if hasattr(t, "numel") and callable(t.numel) else int(np.asarray(t).size)
+    if n != numel:
+        raise ValueError(f"{what}: expected {numel} elements, got {n}")
+
+
+def _need_shape(t, shape, what: str):
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
 class _Obj:
     """Objective with its host arrays kept alive."""
 
@@ -179,6 +198,7 @@ def pyhea_sro_eval(lattice: int, L, M: int, S: int, species, target=None, weight
     """Full evaluation of one configuration: (counts int64, alpha, S, F)."""
     import torch
     lat = make_lattice(lattice, L, M, S)
+    _need(species, n_sites(lattice, L), "species")
     counts = np.zeros((S, M, M), np.int64)
     alpha = np.zeros((S, M, M))
     sf = np.zeros(2)
@@ -195,7 +215,13 @@ def pyhea_sro_eval_batch(lattice: int, L, M: int, S: int, species, counts, targe
     (int32) and optionally S_F[K][2]; asynchronous on the stream."""
     import torch
     lat = make_lattice(lattice, L, M, S)
+    N = n_sites(lattice, L)
+    if species.dim() != 2 or species.shape[1] != N:
+        raise ValueError(f"species: expected shape [K][{N}], got {tuple(species.shape)}")
     K = species.shape[0]
+    _need(counts, K * S * M * M, "counts")
+    if S_F is not None:
+        _need(S_F, 2 * K, "S_F")
     obj = _Obj(target, weight, S, M) if target is not None else None
     _check(lib().pyhea_sro_eval_batch(ctypes.byref(lat), K, _dptr(species, torch.int8),
                                       ctypes.byref(obj.c) if obj else None,
@@ -204,10 +230,20 @@ def pyhea_sro_eval_batch(lattice: int, L, M: int, S: int, species, counts, targe
                                       _stream(stream)))
 
 
+def _pairs_check(pairs):
+    if pairs.dim() != 2 or pairs.shape[1] != 2:
+        raise ValueError(f"pairs: expected shape [n][2], got {tuple(pairs.shape)}")
+
+
 def pyhea_trial_eval(lattice: int, L, M: int, S: int, species, target, weight, pairs, dS,
                      dN=None, stream=None):
     import torch
     lat = make_lattice(lattice, L, M, S)
+    _need(species, n_sites(lattice, L), "species")
+    _pairs_check(pairs)
+    _need(dS, pairs.shape[0], "dS")
+    if dN is not None:
+        _need(dN, pairs.shape[0] * S * M * M, "dN")
     obj = _Obj(target, weight, S, M)
     _check(lib().pyhea_trial_eval(ctypes.byref(lat), ctypes.byref(obj.c), _dptr(species, torch.int8),
                                   pairs.shape[0], _dptr(pairs, torch.int32), _dptr(dS, torch.float64),
@@ -220,6 +256,9 @@ def pyhea_trial_eval_full(lattice: int, L, M: int, S: int, species, target, weig
     non-incremental baseline)."""
     import torch
     lat = make_lattice(lattice, L, M, S)
+    _need(species, n_sites(lattice, L), "species")
+    _pairs_check(pairs)
+    _need(dS, pairs.shape[0], "dS")
     obj = _Obj(target, weight, S, M)
     _check(lib().pyhea_trial_eval_full(ctypes.byref(lat), ctypes.byref(obj.c), _dptr(species, torch.int8),
                                        pairs.shape[0], _dptr(pairs, torch.int32), _dptr(dS, torch.float64),
@@ -232,6 +271,9 @@ def pyhea_mc_run(lattice: int, L, M: int, S: int, target, weight, species, param
     (stats dict, final counts int64 [S][M][M])."""
     import torch
     lat = make_lattice(lattice, L, M, S)
+    _need(species, n_sites(lattice, L), "species")
+    if log is not None and (log.dim() != 2 or log.shape[1] != 4):
+        raise ValueError(f"log: expected shape [cap][4], got {tuple(log.shape)}")
     obj = _Obj(target, weight, S, M)
     st = McStats()
     counts = np.zeros((S, M, M), np.int64)
@@ -295,6 +337,18 @@ def pyhea_mc_batch(problems, species, offsets, params_list, log=None, log_offset
     stats = np.zeros(n, dtype=_STATS_DTYPE)
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
     loff = None if log_offsets is None else np.ascontiguousarray(np.asarray(log_offsets, np.int64))
+    # every chain's slice must hold exactly its sites, and the slices must tile species
+    a = np.where(lat["lattice"] == FCC, 4, 2).astype(np.int64)
+    sizes = a * lat["L"].astype(np.int64).prod(axis=1)
+    if off.shape != (n + 1,) or off[0] != 0 or not np.array_equal(np.diff(off), sizes):
+        raise ValueError("offsets: need n+1 values from 0 whose differences are each chain's site count")
+    _need(species, int(off[-1]), "species")
+    if log is not None:
+        if log.dim() != 2 or log.shape[1] != 4:
+            raise ValueError(f"log: expected shape [cap][4], got {tuple(log.shape)}")
+        if loff is None or loff.shape != (n + 1,) or loff[0] != 0 or np.any(np.diff(loff) < 0) \
+                or loff[-1] > log.shape[0]:
+            raise ValueError("log_offsets: need n+1 non-decreasing values from 0 within the log's rows")
     _check(lib().pyhea_mc_batch(n, _hptr(lat), _hptr(obj), _hptr(pars), _dptr(species, torch.int8), _hptr(off),
                                 _dptr(log, torch.int32) if log is not None else None,
                                 _hptr(loff), _hptr(stats), _stream(stream)))
@@ -304,6 +358,8 @@ def pyhea_mc_batch(problems, species, offsets, params_list, log=None, log_offset
 
 def pyhea_philox4x32_10(ctr, seed: int, out, stream=None):
     import torch
+    _need_shape(ctr, (ctr.shape[0], 4), "ctr")
+    _need_shape(out, tuple(ctr.shape), "out")
     _check(lib().pyhea_philox4x32_10(_dptr(ctr, torch.int32), seed, ctr.shape[0],
                                      _dptr(out, torch.int32), _stream(stream)))
 
@@ -312,6 +368,8 @@ def pyhea_random_configs(N: int, composition, seed: int, iteration: int, slot0: 
     """Random global-search solutions into out[n][N] (device int8)."""
     import torch
     comp = np.ascontiguousarray(np.asarray(composition, dtype=np.int64))
+    if out.dim() != 2 or out.shape[1] != N:
+        raise ValueError(f"out: expected shape [n][{N}], got {tuple(out.shape)}")
     _check(lib().pyhea_random_configs(N, comp.size, _hptr(comp), seed, iteration, slot0, out.shape[0],
                                       _dptr(out, torch.int8), _stream(stream)))
 
@@ -324,8 +382,11 @@ def pyhea_global_search(lattice: int, L, M: int, S: int, target, weight, composi
     Returns (stats dict, best F after each iteration)."""
     import torch
     lat = make_lattice(lattice, L, M, S)
+    _need(best, n_sites(lattice, L), "best")
     obj = _Obj(target, weight, S, M)
     comp = np.ascontiguousarray(np.asarray(composition, dtype=np.int64))
+    if comp.size != M:
+        raise ValueError(f"composition: expected {M} species counts, got {comp.size}")
     p = GlobalParams(n_solutions, iterations, n_refine, 0, discard_frac,
                      make_params(seed, 0, n_trials, B, mode, depth_limit, tau))
     hist = np.zeros(max(iterations, 1))
@@ -354,24 +415,33 @@ class Server:
         h = ctypes.c_void_p()
         _check(lib().pyhea_serve_open(hbm_budget_bytes, max_slots, steps_per_round, ctypes.byref(h)))
         self.h = h
+        self.n_of = {}   # job id -> sites, checked against the poll's output buffer
 
     def pyhea_serve_submit(self, job_id: int, lattice: int, L, M: int, S: int, target, weight,
                            species: np.ndarray, params: McParams):
         lat = make_lattice(lattice, L, M, S)
         obj = _Obj(target, weight, S, M)
         sp = np.ascontiguousarray(species, dtype=np.int8)
+        N = n_sites(lattice, L)
+        _need(sp, N, "species")
         _check(lib().pyhea_serve_submit(self.h, job_id, ctypes.byref(lat), ctypes.byref(obj.c),
                                         ctypes.byref(params), _hptr(sp)))
+        self.n_of[job_id] = N
 
     def pyhea_serve_poll(self, job_id: int, N: int, blocking: bool = True):
         """(status, final species or None, stats dict, (submit, admit, finish) ns)."""
-        out = np.zeros(N, np.int8)
+        if job_id in self.n_of and self.n_of[job_id] != N:
+            raise ValueError(f"job {job_id} has {self.n_of[job_id]} sites, not {N}")
+        # a job this handle did not submit gets no output buffer (the library
+        # answers ENOENT or its status)
+        out = np.zeros(N, np.int8) if job_id in self.n_of else None
         st = McStats()
         times = np.zeros(3, np.int64)
         code = lib().pyhea_serve_poll(self.h, job_id, _hptr(out), ctypes.byref(st), _hptr(times),
                                       1 if blocking else 0)
         if code == EBUSY:
             return code, None, None, None
+        self.n_of.pop(job_id, None)   # a polled job is forgotten
         return code, (out if code == OK else None), st.as_dict(), tuple(int(t) for t in times)
 
     def pyhea_serve_cancel(self, job_id: int) -> int:

@@ -113,6 +113,7 @@ struct Server {
     std::deque<uint64_t> queue;
     std::vector<Job *> resident;
     bool stop = false;
+    int pollers = 0;   // threads blocked in pyhea_serve_poll (close waits for them to leave)
     std::thread worker;
     int64_t n_submitted = 0, n_admitted = 0, n_finished = 0, n_rejected = 0, n_rounds = 0;
     int64_t bytes_resident = 0;
@@ -573,7 +574,12 @@ pyhea_status pyhea_serve_poll(void *server, uint64_t job_id, int8_t *species_out
     auto finished = [&] { return j->phase == kDone || j->phase == kCancelled || j->phase == kFailed; };
     if (!finished()) {
         if (!blocking) return PYHEA_EBUSY;
-        s->cv_done.wait(lk, [&] { return finished() || (s->stop && s->worker_error.size()); });
+        // close() marks every unfinished job cancelled and then waits until no
+        // poller is left inside the server before freeing it
+        ++s->pollers;
+        s->cv_done.wait(lk, [&] { return finished() || s->stop; });
+        --s->pollers;
+        if (s->pollers == 0) s->cv_done.notify_all();
         if (!finished()) {
             set_error("serve_poll: server stopped");
             return PYHEA_EDEVICE;
@@ -642,9 +648,27 @@ pyhea_status pyhea_serve_close(void *server) {
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
     (void)hipSetDevice(s->device);
-    for (Job *j : s->resident) {
-        if (j->mem) (void)hipFreeAsync(j->mem, s->streams[0]);
-        j->mem = nullptr;
+    {
+        // resident jobs give back their device memory; unfinished jobs end as
+        // cancelled; blocked pollers wake, read that and leave before the
+        // server is freed
+        std::unique_lock<std::mutex> lk(s->mu);
+        for (Job *j : s->resident) {
+            if (j->mem) (void)hipFreeAsync(j->mem, s->streams[0]);
+            j->mem = nullptr;
+        }
+        s->resident.clear();
+        const int64_t t = now_ns();
+        for (auto &kv : s->jobs) {
+            Job *j = kv.second.get();
+            if (j->phase == kQueued || j->phase == kResident) {
+                j->phase = kCancelled;
+                j->status = PYHEA_ECANCELLED;
+                j->t_finish = t;
+            }
+        }
+        s->cv_done.notify_all();
+        s->cv_done.wait(lk, [&] { return s->pollers == 0; });
     }
     (void)hipStreamSynchronize(s->streams[0]);
     for (void *p : {s->desc_dev, s->state_dev, s->aux_desc_dev, s->task_dev})

@@ -97,3 +97,57 @@ def test_batch_marshalling_matches_per_chain_structures():
     assert packed.tobytes() == bytes((pb.McParams * len(params))(*params))
     assert pb._STATS_DTYPE.itemsize == ctypes.sizeof(pb.McStats)
     assert pb._STATS_DTYPE.names == tuple(f for f, _ in pb.McStats._fields_)
+
+
+def test_binding_rejects_mis_sized_buffers_before_the_library():
+    """Buffer sizes are checked against the geometry before any pointer is
+    taken: a wrong size raises ValueError, a right size on a CPU tensor gets
+    as far as the device-pointer check (TypeError)."""
+    import numpy as np
+    import torch
+    from paper_2411_18906_amd import binding as b
+    L, M, S = (3, 3, 3), 4, 2
+    N = b.n_sites(b.FCC, L)
+    assert N == 108 and b.n_sites(b.BCC, L) == 54
+    t, w = np.zeros((S, M, M)), np.ones(S)
+    sp_ok, sp_bad = torch.zeros(N, dtype=torch.int8), torch.zeros(N - 1, dtype=torch.int8)
+    with pytest.raises(ValueError):
+        b.pyhea_sro_eval(b.FCC, L, M, S, sp_bad, t, w)
+    with pytest.raises(TypeError):
+        b.pyhea_sro_eval(b.FCC, L, M, S, sp_ok, t, w)
+    with pytest.raises(ValueError):   # counts too small
+        b.pyhea_sro_eval_batch(b.FCC, L, M, S, torch.zeros(2, N, dtype=torch.int8),
+                               torch.zeros(2 * S * M * M - 1, dtype=torch.int32))
+    with pytest.raises(ValueError):   # species rows of the wrong length
+        b.pyhea_sro_eval_batch(b.FCC, L, M, S, torch.zeros(2, N + 1, dtype=torch.int8),
+                               torch.zeros(2 * S * M * M, dtype=torch.int32))
+    with pytest.raises(ValueError):   # log rows must have 4 words
+        b.pyhea_mc_run(b.FCC, L, M, S, t, w, sp_ok, b.make_params(1, 0, 10),
+                       torch.zeros(5, 3, dtype=torch.int32))
+    pairs = torch.zeros(3, 2, dtype=torch.int32)
+    with pytest.raises(ValueError):
+        b.pyhea_trial_eval(b.FCC, L, M, S, sp_ok, t, w, pairs, torch.zeros(2, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        b.pyhea_trial_eval(b.FCC, L, M, S, sp_ok, t, w, torch.zeros(3, 3, dtype=torch.int32),
+                           torch.zeros(3, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        b.pyhea_trial_eval_full(b.FCC, L, M, S, sp_bad, t, w, pairs, torch.zeros(3, dtype=torch.float64))
+    probs = [(b.FCC, L, M, S, t, w), (b.BCC, L, M, S, t, w)]
+    pars = [b.make_params(1, 0, 10), b.make_params(1, 1, 10)]
+    sp2 = torch.zeros(N + N // 2, dtype=torch.int8)
+    with pytest.raises(ValueError):   # offsets that do not match the chains' sizes
+        b.pyhea_mc_batch(probs, sp2, [0, N, N + N // 2 + 1], pars)
+    with pytest.raises(ValueError):   # species shorter than the offsets say
+        b.pyhea_mc_batch(probs, sp2[:-1], [0, N, N + N // 2], pars)
+    with pytest.raises(ValueError):   # log offsets beyond the log
+        b.pyhea_mc_batch(probs, sp2, [0, N, N + N // 2], pars, torch.zeros(4, 4, dtype=torch.int32),
+                         [0, 2, 5])
+    with pytest.raises(TypeError):    # consistent sizes reach the pointer check
+        b.pyhea_mc_batch(probs, sp2, [0, N, N + N // 2], pars)
+    with pytest.raises(ValueError):
+        b.pyhea_philox4x32_10(torch.zeros(4, 3, dtype=torch.int32), 1, torch.zeros(4, 3, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        b.pyhea_random_configs(N, [N // 2, N - N // 2], 1, 0, 0, torch.zeros(2, N - 1, dtype=torch.int8))
+    with pytest.raises(ValueError):
+        b.pyhea_global_search(b.FCC, L, M, S, t, w, [N // 4] * 4, sp_bad, n_solutions=2, iterations=1,
+                              n_refine=1, discard_frac=0.5, seed=1, B=64, n_trials=10)
