@@ -86,7 +86,11 @@ typedef struct {
     int64_t n_trials;      /* T, total trial swaps (the last step may be partial)  */
     int32_t commit_mode;   /* PYHEA_MODE_DISJOINT or PYHEA_MODE_BEST               */
     int32_t depth_limit;   /* stop after this many steps without a commit; 0 = off */
-    double accept_tol;     /* tau: a swap is improving iff dS < -tau (tau >= 0)    */
+    double accept_tol;     /* tau: a trial swap is accepted iff dS < -tau.  tau = 0:
+                              strict improvement; tau > 0: improvement by more
+                              than tau; tau < 0: the threshold acceptance of
+                              Algorithms 2-3 -- swaps that worsen S by less than
+                              -tau are accepted too (null draws never are)       */
 } pyhea_mc_params;
 
 /* Per-chain results. */

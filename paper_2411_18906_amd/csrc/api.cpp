@@ -130,32 +130,8 @@ pyhea_status pyhea_sro_eval_batch(const pyhea_lattice *lat, int64_t n_configs, c
         if (s != PYHEA_OK) return s;
     }
     if (n_configs == 0) return guard(PYHEA_OK);
-    hipStream_t stream = as_stream(stream_);
-    const int E = g.S * g.M * g.M;
-    AsyncBuffer buf;
-    buf.stream = stream;
-    const size_t bad_bytes = (size_t)n_configs * 4;
-    const size_t tw_off = (bad_bytes + 255) & ~size_t(255);
-    PYHEA_HIP(pool_alloc(&buf.ptr, tw_off + (E + kMaxShells) * 8, stream));
-    int32_t *bad = (int32_t *)buf.ptr;
-    double *tdev = (double *)((char *)buf.ptr + tw_off);
-    EvalDesc ed;
-    fill_eval_desc(g, &ed);
-    if (obj) {
-        SmallTable tw{};
-        std::memcpy(tw.v, obj->target, E * 8);
-        std::memcpy(tw.v + E, obj->weight, g.S * 8);
-        PYHEA_HIP(launch_upload(tw, E + kMaxShells, tdev, stream));
-    }
-    bool fused = false;
-    {
-        const pyhea_status s = count_configs(g, n_configs, species_dev, counts_dev, bad, stream, obj ? tdev : nullptr,
-                                             obj ? S_F_dev : nullptr, &fused);
-        if (s != PYHEA_OK) return s;
-    }
-    if (obj && !fused)
-        PYHEA_HIP(launch_objective_epilogue(ed, n_configs, counts_dev, bad, tdev, tdev + E, S_F_dev, nullptr, stream));
-    return guard(PYHEA_OK);
+    const pyhea_status s = eval_batch(g, n_configs, species_dev, obj, counts_dev, S_F_dev, as_stream(stream_));
+    return s == PYHEA_OK ? guard(s) : s;
 }
 
 pyhea_status pyhea_trial_eval(const pyhea_lattice *lat, const pyhea_objective *obj, const int8_t *species_dev,

@@ -110,8 +110,8 @@ pyhea_status check_params(const pyhea_mc_params *p) {
         set_error("depth_limit must be >= 0");
         return PYHEA_EINVAL;
     }
-    if (!std::isfinite(p->accept_tol) || p->accept_tol < 0.0) {
-        set_error("accept_tol must be finite and >= 0");
+    if (!std::isfinite(p->accept_tol)) {
+        set_error("accept_tol must be finite");
         return PYHEA_EINVAL;
     }
     return PYHEA_OK;
@@ -135,21 +135,35 @@ void ratio_table(const Geometry &g, const int64_t *n, double *R) {
                 R[(k * g.M + i) * g.M + j] = (double)g.N / (double)(n[i] * n[j] * (int64_t)g.z[k]);
 }
 
+namespace {
+// the bit-sliced kernel's launch shape for K configurations of g (false: gather)
+bool bit_shape(const Geometry &g, int64_t K, BitDesc *bd) {
+    const int forced = forced_eval_kernel();
+    const int split = forced == 2 ? 1 : forced == 3 ? 4 : 2;
+    return forced != 0 && fill_bit_desc(g, max_lds_per_block(), K, split, bd);
+}
+}  // namespace
+
+size_t count_partial_bytes(const Geometry &g, int64_t K) {
+    BitDesc bd;
+    if (K <= 0 || !bit_shape(g, K, &bd) || bd.nchunks <= 1) return 0;
+    return (size_t)K * bd.nchunks * bd.partial_stride * 4;
+}
+
 pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, int32_t *counts,
-                           int32_t *bad, hipStream_t stream, const double *tw, double *S_F, bool *fused) {
+                           int32_t *bad, hipStream_t stream, const double *tw, double *S_F, bool *fused,
+                           void *partial_scratch) {
     if (fused) *fused = false;
     if (K <= 0) return PYHEA_OK;
-    const int forced = forced_eval_kernel();
     BitDesc bd;
-    const int split = forced == 2 ? 1 : forced == 3 ? 4 : 2;
-    if (forced != 0 && fill_bit_desc(g, max_lds_per_block(), K, split, &bd)) {
-        void *partial = nullptr;
-        if (bd.nchunks > 1)
-            PYHEA_HIP(pool_alloc(&partial, (size_t)K * bd.nchunks * bd.partial_stride * 4, stream));
+    if (bit_shape(g, K, &bd)) {
+        void *partial = partial_scratch;
+        const bool own = partial == nullptr && bd.nchunks > 1;
+        if (own) PYHEA_HIP(pool_alloc(&partial, (size_t)K * bd.nchunks * bd.partial_stride * 4, stream));
         const bool fuse = S_F != nullptr;   // the counting launch finishes Eq. 2-3 too
         const hipError_t e = launch_count_bits(g, bd, K, species, (int32_t *)partial, counts, bad,
                                                fuse ? tw : nullptr, fuse ? S_F : nullptr, stream);
-        if (partial) (void)hipFreeAsync(partial, stream);
+        if (own) (void)hipFreeAsync(partial, stream);
         PYHEA_HIP(e);
         if (fused) *fused = fuse;
         return PYHEA_OK;
@@ -158,6 +172,59 @@ pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, 
     fill_eval_desc(g, &ed);
     PYHEA_HIP(launch_count_gather(ed, K, species, counts, bad, stream));
     return PYHEA_OK;
+}
+
+namespace {
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// eval_batch scratch: flags [K] int32 | target, weight table | partial sums
+struct EvalScratch {
+    size_t tw, partial, total;
+};
+EvalScratch eval_scratch_layout(const Geometry &g, int64_t K) {
+    EvalScratch l;
+    l.tw = align256((size_t)K * 4);
+    l.partial = align256(l.tw + (size_t)kMaxTable * 8);
+    l.total = l.partial + count_partial_bytes(g, K);
+    return l;
+}
+}  // namespace
+
+size_t eval_batch_scratch_bytes(const Geometry &g, int64_t K) { return eval_scratch_layout(g, K).total; }
+
+pyhea_status eval_batch(const Geometry &g, int64_t K, const int8_t *species, const pyhea_objective *obj,
+                        int32_t *counts, double *S_F, hipStream_t stream, void *scratch) {
+    if (K <= 0) return PYHEA_OK;
+    const int E = g.S * g.M * g.M;
+    const EvalScratch lay = eval_scratch_layout(g, K);
+    void *own = nullptr;
+    if (!scratch) {
+        PYHEA_HIP(pool_alloc(&own, lay.total, stream));
+        scratch = own;
+    }
+    char *base = (char *)scratch;
+    int32_t *bad = (int32_t *)base;
+    double *tdev = (double *)(base + lay.tw);
+    pyhea_status st = PYHEA_OK;
+    hipError_t e = hipSuccess;
+    if (obj) {
+        SmallTable tw{};
+        std::memcpy(tw.v, obj->target, E * 8);
+        std::memcpy(tw.v + E, obj->weight, g.S * 8);
+        e = launch_upload(tw, E + kMaxShells, tdev, stream);
+    }
+    bool fused = false;
+    if (e == hipSuccess)
+        st = count_configs(g, K, species, counts, bad, stream, obj ? tdev : nullptr, obj ? S_F : nullptr, &fused,
+                           lay.total > lay.partial ? base + lay.partial : nullptr);
+    if (e == hipSuccess && st == PYHEA_OK && obj && !fused) {
+        EvalDesc ed;
+        fill_eval_desc(g, &ed);
+        e = launch_objective_epilogue(ed, K, counts, bad, tdev, tdev + E, S_F, nullptr, stream);
+    }
+    if (own) (void)hipFreeAsync(own, stream);
+    if (e != hipSuccess) return device_error(e, "eval_batch");
+    return st;
 }
 
 namespace {
@@ -170,8 +237,6 @@ struct DeviceBuffer {
         if (ptr) (void)hipFreeAsync(ptr, stream);
     }
 };
-
-size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Auxiliary streams (default priority, non-blocking) on which launches of
 // different shapes run beside the caller's stream; created once per device,

@@ -63,9 +63,23 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
 // the bit-sliced kernel when it covers the geometry, else the gather kernel.
 // With S_F (and tw = {target, weight} on the device) the objective may be
 // computed by the counting kernel itself; *fused says whether it was.
+// `partial` (optional) is caller-owned scratch for configurations that span
+// several workgroups, at least count_partial_bytes(g, K) bytes; without it the
+// function allocates that scratch itself.
 pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, int32_t *counts,
                            int32_t *bad, hipStream_t stream, const double *tw = nullptr, double *S_F = nullptr,
-                           bool *fused = nullptr);
+                           bool *fused = nullptr, void *partial = nullptr);
+// Scratch bytes count_configs needs for K configurations of g (0 if none).
+size_t count_partial_bytes(const Geometry &g, int64_t K);
+
+// Full evaluation of K configurations (pyhea_sro_eval_batch after argument
+// checks): counts [K][S][M][M] and, with obj, S_F [K][2], on `stream`.
+// `scratch` (optional, eval_batch_scratch_bytes(g, K) bytes, device) holds the
+// per-configuration flags, the target table and the multi-workgroup partial
+// sums; without it they come from the stream-ordered pool.
+pyhea_status eval_batch(const Geometry &g, int64_t K, const int8_t *species, const pyhea_objective *obj,
+                        int32_t *counts, double *S_F, hipStream_t stream, void *scratch = nullptr);
+size_t eval_batch_scratch_bytes(const Geometry &g, int64_t K);
 
 
 }  // namespace pyhea

@@ -404,3 +404,69 @@ def test_mc_batch_rejects_bad_chain(defect):
         pb.pyhea_mc_batch(probs, d, offsets, pars)
     assert "chain 3" in str(e.value)
     np.testing.assert_array_equal(d.cpu().numpy(), bad)   # nothing ran
+
+
+THRESHOLD_CASES = [
+    # lattice, L, M, S, B, mode, T
+    (orc.FCC, (4, 4, 4), 4, 2, 64, 0, 10_000),
+    (orc.FCC, (4, 4, 4), 4, 2, 64, 1, 10_000),
+    (orc.BCC, (5, 4, 4), 3, 3, 48, 0, 6_000),
+    (orc.FCC, (5, 4, 3), 5, 3, 100, 0, 5_001),
+]
+
+
+def threshold_for(lattice, L, M, S, sp, tgt, w, frac=0.2):
+    """-frac x the median |dS| of random swaps of the start (oracle)."""
+    rng = np.random.default_rng(0)
+    ds = []
+    while len(ds) < 100:
+        p, q = (int(x) for x in rng.integers(0, len(sp), size=2))
+        if sp[p] != sp[q]:
+            ds.append(abs(orc.swap_dS(lattice, L, M, S, sp, p, q, tgt, w)))
+    return -frac * float(np.median(ds))
+
+
+@pytest.mark.parametrize("K,variant", [(0, 0), (1, 0), (4, 0), (3, 5), (4, 6), (2, 4)])
+@pytest.mark.parametrize("case", THRESHOLD_CASES)
+def test_threshold_acceptance_matches_oracle(case, K, variant):
+    """tau < 0: swaps that worsen S by less than -tau are accepted too
+    (Algorithms 2-3); every launch shape gives the oracle's trajectory."""
+    lattice, L, M, S, B, mode, T = case
+    rng = np.random.default_rng(sum(L) * 3 + M + B)
+    sp, tgt, w = random_problem(rng, lattice, L, M, S)
+    tau = threshold_for(lattice, L, M, S, sp, tgt, w)
+    pb.pyhea_tune_force_lookahead(K)
+    pb.pyhea_tune_force(variant)
+    try:
+        o, g = run_both(lattice, L, M, S, sp, tgt, w, seed=515, chain=K, T=T, B=B, mode=mode, tau=tau)
+    finally:
+        pb.pyhea_tune_force_lookahead(0)
+        pb.pyhea_tune_force(-1)
+    assert_same_chain(o, g)
+    cur, worse = sp.copy(), 0
+    for _, _, p, q in o[1]:
+        worse += orc.swap_dS(lattice, L, M, S, cur, int(p), int(q), tgt, w) > 0
+        cur[p], cur[q] = cur[q], cur[p]
+    assert worse > 0
+
+
+def test_threshold_acceptance_in_a_batch():
+    """Chains with and without a threshold side by side in one batched call."""
+    chains = wl.config4(n_chains=12, seed=13, n_trials=2000)
+    species = np.concatenate([c.species for c in chains])
+    offsets = np.concatenate([[0], np.cumsum([c.N for c in chains])])
+    taus = [threshold_for(c.lattice, c.L, c.M, c.S, c.species, c.target, c.weight) if i % 2 else 0.0
+            for i, c in enumerate(chains)]
+    d = dev(species)
+    probs = [(c.lattice, c.L, c.M, c.S, c.target, c.weight) for c in chains]
+    pars = [pb.make_params(c.seed, c.chain_id, c.n_trials, c.B, tau=t) for c, t in zip(chains, taus)]
+    stats = pb.pyhea_mc_batch(probs, d, offsets, pars)
+    fin = d.cpu().numpy()
+    for i, c in enumerate(chains):
+        sp_o, _, st_o, _ = orc.mc_run(c.lattice, c.L, c.M, c.S, c.target, c.weight, c.species,
+                                      seed=c.seed, chain_id=c.chain_id, n_trials=c.n_trials, B=c.B,
+                                      tau=taus[i])
+        np.testing.assert_array_equal(fin[offsets[i]:offsets[i + 1]], sp_o)
+        for f in ["trials", "null_trials", "commits", "steps"]:
+            assert stats[i][f] == st_o[f], (i, f)
+        assert stats[i]["S"] == st_o["S"]

@@ -193,3 +193,63 @@ def test_tau_threshold():
         cur[p], cur[q] = cur[q], cur[p]
         S1 = bf.objective(bf.counts_by_offsets(tabs, M, cur), cur, tgt, w, bf.Z[lattice])
         assert S1 - S0 < -tau + 1e-12
+
+
+@pytest.mark.parametrize("lattice,L,S,M,B,mode", [
+    (bf.FCC, (3, 3, 3), 2, 3, 16, orc.MODE_BEST),       # Algorithm 3 with its threshold
+    (bf.BCC, (4, 4, 4), 2, 4, 32, orc.MODE_DISJOINT),
+    (bf.FCC, (3, 3, 3), 2, 3, 1, orc.MODE_BEST),        # B = 1: Algorithm 2 with its threshold
+])
+def test_threshold_acceptance_matches_full_recount_reference(lattice, L, S, M, B, mode):
+    """tau < 0 (Algorithms 2-3 accept a swap that worsens S by less than the
+    threshold): the oracle's log equals the full-recount reference's, every
+    commit has S(after) - S(before) < -tau, and some commits do worsen S."""
+    N, sp, tgt, w = _problem(lattice, L, S, M, seed=23)
+    tabs = bf.neighbor_table(lattice, L, S)
+    T = 60 * B if B > 1 else 400
+    # the threshold: a fifth of the median |dS| of random swaps of the start
+    rng = np.random.default_rng(1)
+    S0 = bf.objective(bf.counts_by_offsets(tabs, M, sp), sp, tgt, w, bf.Z[lattice])
+    ds = []
+    for _ in range(200):
+        p, q = rng.integers(0, N, size=2)
+        if sp[p] != sp[q]:
+            s2 = sp.copy()
+            s2[p], s2[q] = s2[q], s2[p]
+            ds.append(abs(bf.objective(bf.counts_by_offsets(tabs, M, s2), s2, tgt, w, bf.Z[lattice]) - S0))
+    tau = -0.2 * float(np.median(ds))
+    sp_o, log_o, st, cnt = orc.mc_run(lattice, L, M, S, tgt, w, sp, seed=31, chain_id=2,
+                                      n_trials=T, B=B, mode=mode, tau=tau)
+    ref = FullRecountChain(lattice, L, S, M, tgt, w, sp)
+    log_r = ref.run(31, 2, T, B, mode, tau=tau)
+    np.testing.assert_array_equal(log_o, log_r)
+    np.testing.assert_array_equal(sp_o, ref.sp)
+    np.testing.assert_array_equal(cnt, bf.counts_by_offsets(tabs, M, sp_o))
+    cur = sp.copy()
+    worse = 0
+    for _, _, p, q in log_o:
+        a = bf.objective(bf.counts_by_offsets(tabs, M, cur), cur, tgt, w, bf.Z[lattice])
+        cur[p], cur[q] = cur[q], cur[p]
+        b = bf.objective(bf.counts_by_offsets(tabs, M, cur), cur, tgt, w, bf.Z[lattice])
+        assert b - a < -tau + 1e-12
+        worse += b - a > 1e-12
+    assert worse > 0 and len(log_o) > 5
+
+
+def test_threshold_acceptance_never_commits_a_null_draw():
+    """With tau < 0 a draw of two equal species (dS = 0 < -tau) is still a
+    null trial: it is counted and never committed."""
+    lattice, L, S, M = bf.FCC, (3, 3, 3), 2, 2
+    N, sp, tgt, w = _problem(lattice, L, S, M, seed=8)
+    sp_o, log, st, _ = orc.mc_run(lattice, L, M, S, tgt, w, sp, seed=4, chain_id=0, n_trials=640,
+                                  B=64, mode=orc.MODE_DISJOINT, tau=-1.0)
+    assert st["null_trials"] > 0
+    for _, _, p, q in log:
+        assert p != q
+    # a huge threshold accepts every non-null draw that does not conflict
+    assert st["commits"] > 0
+    cur = sp.copy()
+    for _, _, p, q in log:
+        assert cur[p] != cur[q]
+        cur[p], cur[q] = cur[q], cur[p]
+    np.testing.assert_array_equal(cur, sp_o)
