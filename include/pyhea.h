@@ -171,6 +171,24 @@ pyhea_status pyhea_sro_eval_batch(const pyhea_lattice *lat, int64_t n_configs,
                                   int32_t *counts_dev, double *S_F_dev, void *stream);
 
 /*
+ * pyhea_sro_eval_batch for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and asynchrony as pyhea_sro_eval_batch;
+ * the call allocates nothing (no hipMalloc, hipFree or pool allocation).  Its
+ * scratch (per-configuration flags, the target table, partial sums of
+ * configurations that span several workgroups) lives in one fixed 16 MiB
+ * device array per GPU, held until the process ends; the caller still owns
+ * species_dev, counts_dev and S_F_dev.  PYHEA_EINVAL (with a message giving
+ * the bytes needed) when n_configs needs more scratch than the array holds --
+ * about 4 million configurations of one workgroup each, fewer for
+ * configurations split across workgroups.  Calls that overlap on one GPU
+ * share the array and race: order them on one stream.
+ */
+pyhea_status pyhea_sro_eval_batch_noalloc(const pyhea_lattice *lat, int64_t n_configs,
+                                          const int8_t *species_dev, const pyhea_objective *obj,
+                                          int32_t *counts_dev, double *S_F_dev, void *stream);
+
+/*
  * Incremental evaluation of trial swaps against one configuration (Sec. 4.5,
  * Eq. 4; Sec. 4.6.2, Eq. 5): for each pair (p, q) the count change dN of the
  * swap and dS = S(after) - S(before) in the contract above, without applying

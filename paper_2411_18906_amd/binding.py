@@ -28,7 +28,7 @@ EXPORTS = [
     "pyhea_serve_submit", "pyhea_serve_poll", "pyhea_serve_cancel", "pyhea_serve_counters",
     "pyhea_serve_close", "pyhea_philox4x32_10", "pyhea_tune_force",
     "pyhea_tune_force_eval", "pyhea_tune_force_lookahead", "pyhea_global_search",
-    "pyhea_random_configs", "pyhea_trial_eval_full",
+    "pyhea_random_configs", "pyhea_trial_eval_full", "pyhea_sro_eval_batch_noalloc",
 ]
 
 
@@ -94,6 +94,7 @@ def lib():
             "pyhea_last_error": ([], ctypes.c_char_p),
             "pyhea_sro_eval": ([P, P, P, P, P, P, P], i32),
             "pyhea_sro_eval_batch": ([P, i64, P, P, P, P, P], i32),
+            "pyhea_sro_eval_batch_noalloc": ([P, i64, P, P, P, P, P], i32),
             "pyhea_trial_eval": ([P, P, P, i64, P, P, P, P], i32),
             "pyhea_mc_run": ([P, P, P, P, P, i64, P, P, P], i32),
             "pyhea_mc_batch": ([i32, P, P, P, P, P, P, P, P, P], i32),
@@ -213,6 +214,18 @@ def pyhea_sro_eval_batch(lattice: int, L, M: int, S: int, species, counts, targe
                          weight=None, S_F=None, stream=None):
     """Full evaluation of K configurations species[K][N] into counts[K][S][M][M]
     (int32) and optionally S_F[K][2]; asynchronous on the stream."""
+    _eval_batch("pyhea_sro_eval_batch", lattice, L, M, S, species, counts, target, weight, S_F, stream)
+
+
+def pyhea_sro_eval_batch_noalloc(lattice: int, L, M: int, S: int, species, counts, target=None,
+                                 weight=None, S_F=None, stream=None):
+    """pyhea_sro_eval_batch whose scratch is the library's fixed device array
+    (the call allocates no device memory)."""
+    _eval_batch("pyhea_sro_eval_batch_noalloc", lattice, L, M, S, species, counts, target, weight, S_F,
+                stream)
+
+
+def _eval_batch(fn, lattice, L, M, S, species, counts, target, weight, S_F, stream):
     import torch
     lat = make_lattice(lattice, L, M, S)
     N = n_sites(lattice, L)
@@ -223,11 +236,11 @@ def pyhea_sro_eval_batch(lattice: int, L, M: int, S: int, species, counts, targe
     if S_F is not None:
         _need(S_F, 2 * K, "S_F")
     obj = _Obj(target, weight, S, M) if target is not None else None
-    _check(lib().pyhea_sro_eval_batch(ctypes.byref(lat), K, _dptr(species, torch.int8),
-                                      ctypes.byref(obj.c) if obj else None,
-                                      _dptr(counts, torch.int32),
-                                      _dptr(S_F, torch.float64) if S_F is not None else None,
-                                      _stream(stream)))
+    _check(getattr(lib(), fn)(ctypes.byref(lat), K, _dptr(species, torch.int8),
+                              ctypes.byref(obj.c) if obj else None,
+                              _dptr(counts, torch.int32),
+                              _dptr(S_F, torch.float64) if S_F is not None else None,
+                              _stream(stream)))
 
 
 def _pairs_check(pairs):

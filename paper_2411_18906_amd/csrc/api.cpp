@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -108,12 +109,15 @@ pyhea_status pyhea_sro_eval(const pyhea_lattice *lat, const int8_t *species_dev,
     return guard(PYHEA_OK);
 }
 
-pyhea_status pyhea_sro_eval_batch(const pyhea_lattice *lat, int64_t n_configs, const int8_t *species_dev,
-                                  const pyhea_objective *obj, int32_t *counts_dev, double *S_F_dev,
-                                  void *stream_) {
-    Geometry g;
+} // extern "C"
+
+namespace {
+
+// Argument checks shared by the two batched evaluation entry points.
+pyhea_status check_eval_batch(const pyhea_lattice *lat, int64_t n_configs, const int8_t *species_dev,
+                              const pyhea_objective *obj, int32_t *counts_dev, double *S_F_dev, Geometry *g) {
     std::string err;
-    if (build_geometry(lat, &g, &err) != PYHEA_OK) {
+    if (build_geometry(lat, g, &err) != PYHEA_OK) {
         set_error(err);
         return PYHEA_EINVAL;
     }
@@ -125,12 +129,77 @@ pyhea_status pyhea_sro_eval_batch(const pyhea_lattice *lat, int64_t n_configs, c
         set_error("obj and S_F_dev must be given together");
         return PYHEA_EINVAL;
     }
-    if (obj) {
-        const pyhea_status s = check_objective(g, obj);
-        if (s != PYHEA_OK) return s;
+    if (obj) return check_objective(*g, obj);
+    return PYHEA_OK;
+}
+
+// Scratch of pyhea_sro_eval_batch_noalloc: a fixed device array that every GPU
+// the library runs on holds until the process ends.  In host code `scratch`
+// names a host-side stand-in, never the device memory: the device address is
+// taken once per device with hipGetSymbolAddress and only that address is
+// passed to kernels.  Calls that overlap on one device share the array and
+// race; each call overwrites what it reads (no part needs to start at zero).
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+__device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxScratchDevices];
+
+pyhea_status noalloc_scratch(void **addr) {
+    int dev = -1;
+    PYHEA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) {
+        set_error("device index out of range for the fixed scratch table");
+        return PYHEA_EDEVICE;
     }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        PYHEA_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("hipGetSymbolAddress returned no address for the fixed scratch array");
+            return PYHEA_EDEVICE;
+        }
+        g_scratch_addr[dev] = p;
+    }
+    *addr = g_scratch_addr[dev];
+    return PYHEA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pyhea_status pyhea_sro_eval_batch(const pyhea_lattice *lat, int64_t n_configs, const int8_t *species_dev,
+                                  const pyhea_objective *obj, int32_t *counts_dev, double *S_F_dev,
+                                  void *stream_) {
+    Geometry g;
+    pyhea_status s = check_eval_batch(lat, n_configs, species_dev, obj, counts_dev, S_F_dev, &g);
+    if (s != PYHEA_OK) return s;
     if (n_configs == 0) return guard(PYHEA_OK);
-    const pyhea_status s = eval_batch(g, n_configs, species_dev, obj, counts_dev, S_F_dev, as_stream(stream_));
+    s = eval_batch(g, n_configs, species_dev, obj, counts_dev, S_F_dev, as_stream(stream_));
+    return s == PYHEA_OK ? guard(s) : s;
+}
+
+pyhea_status pyhea_sro_eval_batch_noalloc(const pyhea_lattice *lat, int64_t n_configs,
+                                          const int8_t *species_dev, const pyhea_objective *obj,
+                                          int32_t *counts_dev, double *S_F_dev, void *stream_) {
+    Geometry g;
+    pyhea_status s = check_eval_batch(lat, n_configs, species_dev, obj, counts_dev, S_F_dev, &g);
+    if (s != PYHEA_OK) return s;
+    if (n_configs == 0) return guard(PYHEA_OK);
+    const size_t need = eval_batch_scratch_bytes(g, n_configs);
+    if (need > kNoAllocScratchBytes) {
+        set_error("pyhea_sro_eval_batch_noalloc: " + std::to_string(n_configs) + " configurations need " +
+                  std::to_string(need) + " bytes of scratch, more than the fixed " +
+                  std::to_string(kNoAllocScratchBytes) + "-byte array; split the batch");
+        return PYHEA_EINVAL;
+    }
+    void *addr = nullptr;
+    s = noalloc_scratch(&addr);
+    if (s != PYHEA_OK) return s;
+    s = eval_batch(g, n_configs, species_dev, obj, counts_dev, S_F_dev, as_stream(stream_), addr);
     return s == PYHEA_OK ? guard(s) : s;
 }
 
