@@ -83,6 +83,8 @@ def lib():
         L.or_mc_run.restype = i32
         L.or_random_config.argtypes = [i64, i32, P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, P]
         L.or_random_config.restype = i32
+        L.or_map_sites.argtypes = [i32, P, i32, P, ctypes.c_double, i64, P, P, P, P]
+        L.or_map_sites.restype = i32
         _lib = L
     return _lib
 
@@ -275,3 +277,25 @@ def global_search(lattice: int, L, M: int, S: int, target, weight, composition, 
             pool[s] = refined[s][3]
         kept = R
     return best, best_S, best_F, np.array(history), st
+
+
+MAP_ERRORS = {1: "atom count differs from the number of sites", 2: "an atom lies farther than max_disp from every site",
+              3: "two atoms share a site", 4: "a type lies outside [0, M)"}
+
+
+def map_sites(lattice: int, L, M: int, box, max_disp: float, xyz, types):
+    """Nearest-site assignment of an external structure (brute force over all
+    sites, periodic minimum image, ties to the lower site id): returns
+    (species[N] int8, site_of_atom[n] int64); raises ValueError with the reason
+    (1 count, 2 displacement, 3 double occupancy, 4 type) in its args."""
+    xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+    types = np.ascontiguousarray(np.asarray(types, dtype=np.int8))
+    box = np.ascontiguousarray(np.asarray(box, dtype=np.float64).reshape(3))
+    N = n_sites(lattice, L)
+    sp = np.zeros(N, np.int8)
+    site = np.zeros(xyz.shape[0], np.int64)
+    rc = lib().or_map_sites(lattice, _p(_L(L)), M, _p(box), float(max_disp), xyz.shape[0], _p(xyz), _p(types),
+                            _p(sp), _p(site))
+    if rc:
+        raise ValueError(MAP_ERRORS.get(rc, "allocation failed"), rc)
+    return sp, site

@@ -625,3 +625,62 @@ int or_random_config(int64_t N, int M, const int64_t *composition, uint64_t seed
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Structures from other codes (the application workflow of Sec. 2.3, step  */
+/* (3): a relaxed or MD structure is analysed for its SRO).  Each atom is    */
+/* assigned to the lattice site nearest to it under periodic minimum-image  */
+/* distances, by brute force over all sites; ties go to the lower site id.  */
+/* box[3] are the Cartesian edge lengths of the orthorhombic supercell of   */
+/* L[0] x L[1] x L[2] conventional cells (site half-unit position h maps to  */
+/* h * box / (2 L)).  Returns 0, or 1 if n != number of sites, 2 if some     */
+/* atom lies farther than max_disp from every site, 3 if two atoms share a   */
+/* site, 4 if a type lies outside [0, M).  species_out[site] = types[atom],  */
+/* site_out[atom] = its site.                                                */
+/* ------------------------------------------------------------------------ */
+int or_map_sites(int lattice, const int *L, int M, const double *box, double max_disp, int64_t n,
+                 const double *xyz, const int8_t *types, int8_t *species_out, int64_t *site_out) {
+    const int64_t N = or_n_sites(lattice, L);
+    if (n != N) return 1;
+    int64_t *owner = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    if (!owner) return 5;
+    for (int64_t p = 0; p < N; ++p) owner[p] = -1;
+    int rc = 0;
+    for (int64_t a = 0; a < n && rc == 0; ++a) {
+        if (types[a] < 0 || types[a] >= M) {
+            rc = 4;
+            break;
+        }
+        int64_t best = -1;
+        double best_d2 = 0.0;
+        for (int64_t p = 0; p < N; ++p) {
+            int pos[3];
+            or_site_pos(lattice, L, p, pos);
+            double d2 = 0.0;
+            for (int ax = 0; ax < 3; ++ax) {
+                const double site = (double)pos[ax] * box[ax] / (double)(2 * L[ax]);
+                double d = xyz[3 * a + ax] - site;
+                d -= box[ax] * floor(d / box[ax] + 0.5); /* minimum image */
+                d2 += d * d;
+            }
+            if (best < 0 || d2 < best_d2) {
+                best = p;
+                best_d2 = d2;
+            }
+        }
+        if (best_d2 > max_disp * max_disp) {
+            rc = 2;
+            break;
+        }
+        if (owner[best] >= 0) {
+            rc = 3;
+            break;
+        }
+        owner[best] = a;
+        site_out[a] = best;
+    }
+    if (rc == 0)
+        for (int64_t p = 0; p < N; ++p) species_out[p] = types[owner[p]];
+    free(owner);
+    return rc;
+}
