@@ -189,6 +189,32 @@ pyhea_status pyhea_sro_eval_batch_noalloc(const pyhea_lattice *lat, int64_t n_co
                                           int32_t *counts_dev, double *S_F_dev, void *stream);
 
 /*
+ * Nearest-site assignment of a structure from another code (the analysis step
+ * of the application workflow, Sec. 2.3: a configuration relaxed or simulated
+ * by LAMMPS or DFT is read back onto the lattice so that its SRO can be
+ * evaluated with pyhea_sro_eval and used as a target).  Each atom goes to the
+ * lattice site nearest to it in the Cartesian metric under periodic minimum
+ * images; site half-unit position h lies at h * box / (2 L) per axis.
+ *   box_host          [3] edge lengths of the orthorhombic supercell of
+ *                     L[0] x L[1] x L[2] conventional cells (same unit as xyz).
+ *   max_disp          largest accepted distance of an atom from its site.
+ *   n_atoms           must equal the number of sites N.
+ *   xyz_dev           [n_atoms][3] double Cartesian positions (any periodic
+ *                     image), device.
+ *   types_dev         [n_atoms] int8 species ids in [0, M), device.
+ *   species_dev       [N] int8 out: the species on each site, device.
+ *   atom_of_site_dev  [N] int32 out: the atom on each site, or NULL.
+ * Synchronous.  PYHEA_EINVAL when n_atoms != N, an atom lies farther than
+ * max_disp from every site, two atoms are nearest to one site (a vacancy
+ * elsewhere), or a type lies outside [0, M); the message says which.  Exact
+ * ties between two sites (an atom equidistant from both) are resolved by the
+ * decoding order, not by site id.
+ */
+pyhea_status pyhea_map_sites(const pyhea_lattice *lat, const double *box_host, double max_disp,
+                             int64_t n_atoms, const double *xyz_dev, const int8_t *types_dev,
+                             int8_t *species_dev, int32_t *atom_of_site_dev, void *stream);
+
+/*
  * Incremental evaluation of trial swaps against one configuration (Sec. 4.5,
  * Eq. 4; Sec. 4.6.2, Eq. 5): for each pair (p, q) the count change dN of the
  * swap and dS = S(after) - S(before) in the contract above, without applying
@@ -350,9 +376,15 @@ pyhea_status pyhea_tune_force(int32_t variant);
  * geometry, else gather), 0 = gather, 1 = bit-sliced where possible (a
  * configuration whose layers would take more than half of a CU's LDS is cut
  * along z so that two workgroups share each CU), 2 = bit-sliced without that
- * cut, 3 = bit-sliced cut for four workgroups per CU.  All give identical
- * counts. */
+ * cut, 3 = bit-sliced cut for four workgroups per CU, 4 = streaming where it
+ * covers the geometry (persistent workgroups walk whole configurations along
+ * z while the next layers load).  All give identical counts. */
 pyhea_status pyhea_tune_force_eval(int32_t kernel);
+
+/* Launch shape of the streaming evaluation: centre layers per group (0 =
+ * automatic, else 1..8) and workgroup size (0 = automatic, 256 or 512).
+ * Process-wide; shapes never change results; EINVAL outside those values. */
+pyhea_status pyhea_tune_force_stream(int32_t layers_per_group, int32_t threads);
 
 /* Steps whose candidates one pass of the MC kernel evaluates at once: 0 =
  * automatic (the largest value up to 8 whose block still lets every chain of

@@ -29,6 +29,7 @@ EXPORTS = [
     "pyhea_serve_close", "pyhea_philox4x32_10", "pyhea_tune_force",
     "pyhea_tune_force_eval", "pyhea_tune_force_lookahead", "pyhea_global_search",
     "pyhea_random_configs", "pyhea_trial_eval_full", "pyhea_sro_eval_batch_noalloc",
+    "pyhea_tune_force_stream", "pyhea_map_sites",
 ]
 
 
@@ -107,6 +108,8 @@ def lib():
             "pyhea_philox4x32_10": ([P, u64, i64, P, P], i32),
             "pyhea_tune_force": ([i32], i32),
             "pyhea_tune_force_eval": ([i32], i32),
+            "pyhea_tune_force_stream": ([i32, i32], i32),
+            "pyhea_map_sites": ([P, P, ctypes.c_double, i64, P, P, P, P, P], i32),
             "pyhea_tune_force_lookahead": ([i32], i32),
             "pyhea_global_search": ([P, P, P, P, P, P, P, P], i32),
             "pyhea_random_configs": ([i64, i32, P, u64, ctypes.c_uint32, ctypes.c_uint32, i32, P, P], i32),
@@ -221,7 +224,8 @@ def pyhea_sro_eval_batch_noalloc(lattice: int, L, M: int, S: int, species, count
                                  weight=None, S_F=None, stream=None):
     """pyhea_sro_eval_batch whose scratch is the library's fixed device array
     (the call allocates no device memory)."""
-    _eval_batch("pyhea_sro_eval_batch_noalloc", lattice, L, M, S, species, counts, target, weight, S_F,
+    _eval_batch("pyhea_sro_eval_batch_noalloc",
+    "pyhea_tune_force_stream", "pyhea_map_sites", lattice, L, M, S, species, counts, target, weight, S_F,
                 stream)
 
 
@@ -241,6 +245,26 @@ def _eval_batch(fn, lattice, L, M, S, species, counts, target, weight, S_F, stre
                               _dptr(counts, torch.int32),
                               _dptr(S_F, torch.float64) if S_F is not None else None,
                               _stream(stream)))
+
+
+def pyhea_map_sites(lattice: int, L, M: int, S: int, box, max_disp: float, xyz, types, species,
+                    atom_of_site=None, stream=None):
+    """Nearest-site assignment of an external structure: xyz [N][3] float64 and
+    types [N] int8 (device) onto species [N] int8 (device, written); optional
+    atom_of_site [N] int32 (device, written)."""
+    import torch
+    lat = make_lattice(lattice, L, M, S)
+    N = n_sites(lattice, L)
+    _need_shape(xyz, (N, 3), "xyz")
+    _need(types, N, "types")
+    _need(species, N, "species")
+    if atom_of_site is not None:
+        _need(atom_of_site, N, "atom_of_site")
+    b = np.ascontiguousarray(np.asarray(box, dtype=np.float64).reshape(3))
+    _check(lib().pyhea_map_sites(ctypes.byref(lat), _hptr(b), float(max_disp), N, _dptr(xyz, torch.float64),
+                                 _dptr(types, torch.int8), _dptr(species, torch.int8),
+                                 _dptr(atom_of_site, torch.int32) if atom_of_site is not None else None,
+                                 _stream(stream)))
 
 
 def _pairs_check(pairs):
@@ -415,6 +439,10 @@ def pyhea_tune_force(variant: int):
 
 def pyhea_tune_force_eval(kernel: int):
     _check(lib().pyhea_tune_force_eval(kernel))
+
+
+def pyhea_tune_force_stream(layers_per_group: int, threads: int):
+    _check(lib().pyhea_tune_force_stream(int(layers_per_group), int(threads)))
 
 
 def pyhea_tune_force_lookahead(steps: int):

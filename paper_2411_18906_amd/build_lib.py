@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpyhea.so")
-SOURCES = ["geometry.cpp", "runtime.cpp", "autotune.cpp", "api.cpp", "serve.cpp",
+SOURCES = ["geometry.cpp", "runtime.cpp", "autotune.cpp", "api.cpp", "serve.cpp", "sites.hip",
            "sro_kernels.hip", "sro_bits.hip", "mc_kernels.hip"]
 ARCH = os.environ.get("PYHEA_OFFLOAD_ARCH", "gfx950")
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -14,6 +15,7 @@
 #include "autotune.h"
 #include "pyhea.h"
 #include "runtime.h"
+#include "sites.h"
 
 namespace pyhea {
 const std::string &last_error();
@@ -201,6 +203,74 @@ pyhea_status pyhea_sro_eval_batch_noalloc(const pyhea_lattice *lat, int64_t n_co
     if (s != PYHEA_OK) return s;
     s = eval_batch(g, n_configs, species_dev, obj, counts_dev, S_F_dev, as_stream(stream_), addr);
     return s == PYHEA_OK ? guard(s) : s;
+}
+
+pyhea_status pyhea_map_sites(const pyhea_lattice *lat, const double *box_host, double max_disp, int64_t n_atoms,
+                             const double *xyz_dev, const int8_t *types_dev, int8_t *species_dev,
+                             int32_t *atom_of_site_dev, void *stream_) {
+    Geometry g;
+    std::string err;
+    if (build_geometry(lat, &g, &err) != PYHEA_OK) {
+        set_error(err);
+        return PYHEA_EINVAL;
+    }
+    if (!box_host || !species_dev || (n_atoms > 0 && (!xyz_dev || !types_dev))) {
+        set_error("box_host, species_dev, xyz_dev and types_dev must not be NULL");
+        return PYHEA_EINVAL;
+    }
+    for (int ax = 0; ax < 3; ++ax)
+        if (!std::isfinite(box_host[ax]) || box_host[ax] <= 0.0) {
+            set_error("box edge lengths must be finite and > 0");
+            return PYHEA_EINVAL;
+        }
+    if (!std::isfinite(max_disp) || max_disp < 0.0) {
+        set_error("max_disp must be finite and >= 0");
+        return PYHEA_EINVAL;
+    }
+    if (n_atoms != g.N) {
+        set_error("n_atoms (" + std::to_string(n_atoms) + ") must equal the number of lattice sites (" +
+                  std::to_string(g.N) + ")");
+        return PYHEA_EINVAL;
+    }
+    if (g.N > INT32_MAX) {
+        set_error("too many sites for 32-bit atom indices");
+        return PYHEA_EINVAL;
+    }
+    hipStream_t stream = as_stream(stream_);
+    SiteMapDesc md{};
+    md.lattice = g.lattice;
+    md.A = g.A;
+    for (int ax = 0; ax < 3; ++ax) {
+        md.L[ax] = g.L[ax];
+        md.scale[ax] = 2.0 * g.L[ax] / box_host[ax];
+    }
+    md.M = g.M;
+    md.N = g.N;
+    md.max_disp2 = max_disp * max_disp;
+    // device block: flags [4] | owner [N] (unless the caller's)
+    AsyncBuffer buf;
+    buf.stream = stream;
+    const size_t own = atom_of_site_dev ? 0 : (size_t)g.N * 4;
+    PYHEA_HIP(pool_alloc(&buf.ptr, 256 + own, stream));
+    int32_t *flags = (int32_t *)buf.ptr;
+    int32_t *owner = atom_of_site_dev ? atom_of_site_dev : (int32_t *)((char *)buf.ptr + 256);
+    PYHEA_HIP(launch_map_sites(md, n_atoms, xyz_dev, types_dev, owner, flags, species_dev, stream));
+    int32_t fh[4] = {0, 0, 0, 0};
+    PYHEA_HIP(hipMemcpyAsync(fh, flags, sizeof(fh), hipMemcpyDeviceToHost, stream));
+    PYHEA_HIP(hipStreamSynchronize(stream));
+    if (fh[0]) {
+        set_error("an atom lies farther than max_disp from every lattice site");
+        return PYHEA_EINVAL;
+    }
+    if (fh[2]) {
+        set_error("atom types must lie in [0, n_species)");
+        return PYHEA_EINVAL;
+    }
+    if (fh[1] || fh[3]) {
+        set_error("two atoms are nearest to one lattice site (another site is vacant)");
+        return PYHEA_EINVAL;
+    }
+    return guard(PYHEA_OK);
 }
 
 pyhea_status pyhea_trial_eval(const pyhea_lattice *lat, const pyhea_objective *obj, const int8_t *species_dev,
@@ -538,12 +608,21 @@ pyhea_status pyhea_philox4x32_10(const uint32_t *ctr_dev, uint64_t seed, int64_t
 }
 
 pyhea_status pyhea_tune_force_eval(int32_t kernel) {
-    if (kernel < -1 || kernel > 3) {
-        set_error("kernel must be -1 (automatic), 0 (gather), 1 (bit-sliced), 2 (bit-sliced, no z split) or 3 "
-                  "(bit-sliced, four workgroups per CU)");
+    if (kernel < -1 || kernel > 4) {
+        set_error("kernel must be -1 (automatic), 0 (gather), 1 (bit-sliced), 2 (bit-sliced, no z split), 3 "
+                  "(bit-sliced, four workgroups per CU) or 4 (streaming)");
         return PYHEA_EINVAL;
     }
     set_forced_eval_kernel(kernel);
+    return guard(PYHEA_OK);
+}
+
+pyhea_status pyhea_tune_force_stream(int32_t layers_per_group, int32_t threads) {
+    if (layers_per_group < 0 || layers_per_group > 8 || (threads != 0 && threads != 256 && threads != 512)) {
+        set_error("layers_per_group must be 0 (automatic) or 1..8 and threads 0 (automatic), 256 or 512");
+        return PYHEA_EINVAL;
+    }
+    set_forced_stream_shape(layers_per_group, threads);
     return guard(PYHEA_OK);
 }
 
