@@ -13,6 +13,7 @@ namespace {
 std::mutex g_mu;
 int g_forced = -1;
 int g_forced_eval = -1;
+int g_stream_G = 0, g_stream_threads = 0;
 int g_forced_lookahead = 0;
 }  // namespace
 
@@ -100,6 +101,18 @@ int forced_eval_kernel() {
 void set_forced_eval_kernel(int v) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_forced_eval = v;
+}
+
+void forced_stream_shape(int *layers_per_group, int *threads) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    *layers_per_group = g_stream_G;
+    *threads = g_stream_threads;
+}
+
+void set_forced_stream_shape(int layers_per_group, int threads) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_stream_G = layers_per_group;
+    g_stream_threads = threads;
 }
 
 int forced_lookahead() {

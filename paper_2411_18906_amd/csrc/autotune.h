@@ -41,9 +41,12 @@ int wave_budget(int n_chains);
 int forced_variant();
 void set_forced_variant(int v);
 // Full-evaluation kernel forced through pyhea_tune_force_eval (-1 = automatic,
-// 0 = gather, 1 = bit-sliced).
+// 0 = gather, 1-3 = bit-sliced, 4 = streaming).
 int forced_eval_kernel();
 void set_forced_eval_kernel(int v);
+// Streaming evaluation shape forced through pyhea_tune_force_stream (0 = automatic).
+void forced_stream_shape(int *layers_per_group, int *threads);
+void set_forced_stream_shape(int layers_per_group, int threads);
 // Steps per pass forced through pyhea_tune_force_lookahead (0 = automatic).
 int forced_lookahead();
 void set_forced_lookahead(int k);

@@ -70,6 +70,17 @@ int max_lds_per_block() {
     return v;
 }
 
+int cu_count() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    static int cached[64] = {0};
+    if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
+    int v = 256;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    if (dev >= 0 && dev < 64) cached[dev] = v;
+    return v;
+}
+
 pyhea_status check_objective(const Geometry &g, const pyhea_objective *obj) {
     if (!obj || !obj->target || !obj->weight) {
         set_error("objective, target and weight must not be NULL");
@@ -142,11 +153,20 @@ bool bit_shape(const Geometry &g, int64_t K, BitDesc *bd) {
     const int split = forced == 2 ? 1 : forced == 3 ? 4 : 2;
     return forced != 0 && fill_bit_desc(g, max_lds_per_block(), K, split, bd);
 }
+
+// the streaming kernel's launch shape for K configurations of g (false: not taken)
+bool stream_shape(const Geometry &g, int64_t K, StreamDesc *sd) {
+    if (forced_eval_kernel() != 4) return false;
+    int G = 0, threads = 0;
+    forced_stream_shape(&G, &threads);
+    return fill_stream_desc(g, max_lds_per_block(), cu_count(), K, G, threads, sd);
+}
 }  // namespace
 
 size_t count_partial_bytes(const Geometry &g, int64_t K) {
     BitDesc bd;
-    if (K <= 0 || !bit_shape(g, K, &bd) || bd.nchunks <= 1) return 0;
+    StreamDesc sd;
+    if (K <= 0 || stream_shape(g, K, &sd) || !bit_shape(g, K, &bd) || bd.nchunks <= 1) return 0;
     return (size_t)K * bd.nchunks * bd.partial_stride * 4;
 }
 
@@ -155,6 +175,14 @@ pyhea_status count_configs(const Geometry &g, int64_t K, const int8_t *species, 
                            void *partial_scratch) {
     if (fused) *fused = false;
     if (K <= 0) return PYHEA_OK;
+    StreamDesc sd;
+    if (stream_shape(g, K, &sd)) {
+        const bool fuse = S_F != nullptr;   // the counting launch finishes Eq. 2-3 too
+        PYHEA_HIP(launch_count_stream(g, sd, K, species, counts, bad, fuse ? tw : nullptr, fuse ? S_F : nullptr,
+                                      stream));
+        if (fused) *fused = fuse;
+        return PYHEA_OK;
+    }
     BitDesc bd;
     if (bit_shape(g, K, &bd)) {
         void *partial = partial_scratch;

@@ -28,6 +28,35 @@ struct BitDesc {
     int32_t tab_r[4][kMaxOffsets / 2];      // funnel-shift amount
 };
 
+// Streaming form (batches): one workgroup per configuration at a time, z
+// layers walked in groups of G while the next chunk's bytes arrive.
+struct StreamDesc {
+    int32_t Lx, Ly, Lz;     // four-site cells per axis
+    int32_t RS, LW, PADW, PW, cw0, NCW;   // as in BitDesc
+    int32_t G;              // centre layers per group
+    int32_t ngroups;        // ceil(Lz / G)
+    int32_t ndma;           // 64-position load blocks per staged layer
+    int32_t raw_dw;         // dwords per staged layer (64 * ndma)
+    int32_t slot_dw;        // dwords per plane slot (4 * PW * planes padded to even)
+    int32_t o_planes, o_cmask, o_red2, o_red, o_epi;   // LDS offsets (dwords)
+    int32_t lds_bytes;
+    int32_t threads;
+    int32_t maxd;           // load blocks per lane the kernel holds offsets for
+    int32_t grid;           // persistent workgroups
+    uint32_t N;
+    int32_t zk[kMaxShells];
+    int32_t hs[4][2][kMaxShells + 1];   // per basis and layer step dz: start of shell k's half offsets
+    int32_t tab[4][kMaxOffsets / 2];     // (dword delta within a layer slot) * 32 + funnel shift
+};
+
+// Fills sd for a batch of K configurations; false if the streaming kernel does
+// not cover the geometry (same lattices as the bit-sliced kernel).  G and
+// threads = 0 pick the launch shape automatically.
+bool fill_stream_desc(const Geometry &g, int lds_budget, int n_cus, int64_t K, int G, int threads, StreamDesc *sd);
+
+hipError_t launch_count_stream(const Geometry &g, const StreamDesc &sd, int64_t K, const int8_t *species,
+                               int32_t *counts, int32_t *bad, const double *tw, double *S_F, hipStream_t stream);
+
 // Fills bd; false if the bit-sliced kernel does not cover this geometry (it
 // covers FCC, and BCC with an even number of cells along x, for shells whose
 // neighbours lie at most one cell away).

@@ -99,7 +99,7 @@ BATCH_SHAPES = [
 ]
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2, 3])
+@pytest.mark.parametrize("kernel", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("lattice,L,M,S,K", BATCH_SHAPES)
 def test_sro_eval_batch_matches_oracle(lattice, L, M, S, K, kernel):
     pb.pyhea_tune_force_eval(kernel)
@@ -131,6 +131,48 @@ def _batch_case(lattice, L, M, S, K):
         np.testing.assert_array_equal(c[k], want)
         _, _, S_o, F_o = orc.alpha_objective(lattice, L, M, S, cfg[k], want, tgt, w)
         assert sf[k, 0] == S_o and sf[k, 1] == F_o
+
+
+STREAM_CASES = [
+    # (lattice, L, M, S, K): several configurations per persistent workgroup,
+    # layer groups that divide Lz and ragged ones, a chunk 0 covering all layers
+    (orc.FCC, (5, 4, 7), 4, 2, 2600), (orc.FCC, (6, 3, 3), 5, 3, 2300), (orc.BCC, (8, 5, 4), 3, 2, 2400),
+    (orc.FCC, (9, 7, 2), 6, 2, 700), (orc.FCC, (40, 40, 9), 4, 2, 40), (orc.FCC, (20, 20, 20), 5, 3, 30),
+]
+
+
+@pytest.mark.parametrize("G,threads", [(1, 256), (2, 256), (3, 512), (5, 256), (8, 512)])
+@pytest.mark.parametrize("lattice,L,M,S,K", STREAM_CASES)
+def test_stream_eval_shapes_match_oracle(lattice, L, M, S, K, G, threads):
+    """The streaming evaluation under forced launch shapes (layers per group,
+    workgroup size): every configuration's counts against the oracle, S and F
+    on a sample."""
+    N = orc.n_sites(lattice, L)
+    cfg = wl.iid_configs(N, M, K, seed=K + G)
+    rng = np.random.default_rng(G)
+    tgt = rng.uniform(-0.2, 0.2, (S, M, M))
+    w = rng.uniform(0.1, 1.0, S)
+    counts = torch.zeros((K, S, M, M), dtype=torch.int32, device="cuda")
+    SF = torch.zeros((K, 2), dtype=torch.float64, device="cuda")
+    pb.pyhea_tune_force_eval(4)
+    pb.pyhea_tune_force_stream(G, threads)
+    try:
+        pb.pyhea_sro_eval_batch(lattice, L, M, S, dev(cfg), counts, tgt, w, SF)
+        torch.cuda.synchronize()
+    finally:
+        pb.pyhea_tune_force_eval(-1)
+        pb.pyhea_tune_force_stream(0, 0)
+    c = counts.cpu().numpy()
+    sf = SF.cpu().numpy()
+    for k in range(K):
+        if (np.bincount(cfg[k], minlength=M) == 0).any():
+            assert np.all(np.isnan(sf[k]))
+            continue
+        want = orc.counts(lattice, L, M, S, cfg[k])
+        np.testing.assert_array_equal(c[k], want, err_msg=f"configuration {k}")
+        if k % 97 == 0 or k == K - 1:
+            _, _, S_o, F_o = orc.alpha_objective(lattice, L, M, S, cfg[k], want, tgt, w)
+            assert sf[k, 0] == S_o and sf[k, 1] == F_o
 
 
 def test_sro_eval_batch_whole_configurations_per_workgroup():
