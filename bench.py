@@ -47,13 +47,15 @@ def parse():
     ap.add_argument("--eval-configs", type=int, default=32768)
     ap.add_argument("--chains", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="eval,eval3,lat,chain,batch")
+    ap.add_argument("--legs", default="eval,eval3,lat,chain,chain1,chain3,batch,copy")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (one after another) chains")
     ap.add_argument("--serve-jobs", type=int, default=2000, help="served jobs (0 = skip serving)")
     ap.add_argument("--serve-budget-mb", type=int, default=512)
     ap.add_argument("--no-global", action="store_true", help="skip the global search leg")
     ap.add_argument("--no-baseline", action="store_true", help="skip the incremental-vs-full leg")
-    ap.add_argument("--serve-load", type=float, default=0.7, help="offered load / batched capacity")
+    ap.add_argument("--serve-load", type=float, default=0.7, help="offered load / measured serving capacity")
+    ap.add_argument("--no-best", action="store_true", help="skip the DISJOINT vs BEST comparison")
+    ap.add_argument("--no-cpu-batch", action="store_true", help="skip the all-core oracle run of the batched chains")
     return ap.parse_args()
 
 
@@ -84,6 +86,96 @@ def cpu_baseline(p, budget_s: float = 12.0):
                       f"{n_eval} full evaluations of one 32,000-site configuration",
             "full_eval_sites_per_s": n_eval * p.N / de,
             "full_eval_GBps": n_eval * p.N / de / 1e9}
+
+
+def progress(msg: str):
+    """A progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _oracle_chain(job):
+    """Worker: one oracle chain (the oracle as it stands)."""
+    from oracle import oracle as orc
+    j = dict(job)
+    args = [j.pop(k) for k in ("lattice", "L", "M", "S", "target", "weight", "species")]
+    t0 = time.perf_counter()
+    orc.mc_run(*args, **j)
+    return time.perf_counter() - t0
+
+
+def cpu_batch_baseline(chains, n_sample: int = 128):
+    """The oracle on the batched chains across all host cores: the first
+    n_sample chains of the 512 (10^5 trials each), one process per core."""
+    import multiprocessing
+    import platform
+    from concurrent.futures import ProcessPoolExecutor
+    cores = max(1, min(16, os.cpu_count() or 1))   # the box grants a share of 16 CPUs
+    sample = chains[:n_sample]
+    jobs = [dict(lattice=c.lattice, L=tuple(c.L), M=c.M, S=c.S, target=c.target, weight=c.weight,
+                 species=c.species, seed=c.seed, chain_id=c.chain_id, n_trials=c.n_trials, B=c.B)
+            for c in sample]
+    with ProcessPoolExecutor(max_workers=cores, mp_context=multiprocessing.get_context("spawn")) as ex:
+        list(ex.map(_oracle_chain, jobs[:cores]))   # warm the workers (imports, library load)
+        t0 = time.perf_counter()
+        per = list(ex.map(_oracle_chain, jobs))
+        wall = time.perf_counter() - t0
+    trials = sum(c.n_trials for c in sample)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": trials / wall, "unit": "trial swaps/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {len(sample)} of the {len(chains)} batched chains ({trials} trials), "
+                      f"one oracle process per core",
+            "nproc": os.cpu_count(), "cpu_model": model or platform.processor(),
+            "wall_s": wall, "cpu_s": float(sum(per))}
+
+
+def best_vs_disjoint(pb, p, torch, t_disjoint_s, F_disjoint):
+    """Paper-literal BEST commits (one swap per step, Eq. 6) against the
+    DISJOINT commits of the timed FCC 20^3 chain: the fewest trials (to 1/16)
+    with which BEST reaches the DISJOINT chain's final F, and the time it takes.
+    A BEST chain with a smaller budget is a prefix of one with a larger budget
+    (counter-based draws), so F falls monotonically with the budget."""
+    d = torch.empty(p.N, dtype=torch.int8, device="cuda")
+    src = torch.from_numpy(p.species).cuda()
+
+    def run(T):
+        d.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, _ = pb.pyhea_mc_run(p.lattice, p.L, p.M, p.S, p.target, p.weight, d,
+                                pb.make_params(p.seed, p.chain_id, T, p.B, mode=pb.MODE_BEST), None)
+        return st, time.perf_counter() - t0
+
+    T_cap = 32 * p.n_trials
+    lo, hi = 0, p.n_trials
+    st, _ = run(hi)
+    F_at_T = st["F"]
+    while st["F"] > F_disjoint and hi < T_cap:
+        lo, hi = hi, min(2 * hi, T_cap)
+        st, _ = run(hi)
+    reached = st["F"] <= F_disjoint
+    if reached:
+        step = max(p.B, hi // 16)
+        while hi - lo > step:
+            mid = (lo + hi) // 2 // p.B * p.B
+            if mid <= lo:
+                break
+            if run(mid)[0]["F"] <= F_disjoint:
+                hi = mid
+            else:
+                lo = mid
+    st, t_best = run(hi)
+    return {"disjoint_s": t_disjoint_s, "disjoint_final_F": F_disjoint, "best_F_at_equal_trials": F_at_T,
+            "best_reached_disjoint_F": bool(reached), "best_trials": hi, "best_s": t_best,
+            "best_final_F": st["F"], "disjoint_speedup_at_equal_F": t_best / t_disjoint_s if reached else None,
+            "workload": "FCC 20^3, 5 species, shells 1-3, B = 64; BEST commits the best improving swap "
+                        "of a step, DISJOINT every non-conflicting one"}
 
 
 def recorded(profile: str, source: str, key: str):
@@ -122,11 +214,16 @@ def recorded_traffic():
 
 def serve(pb, wl, n_jobs, capacity_trials_per_s, load, budget_mb):
     """Poisson arrivals of jobs (2,000-2,000,000 sites, 10^4-10^7 trials) at
-    `load` times the measured batched capacity; latency = completion - arrival."""
+    `load` times the given capacity (load 0: every job arrives at once, which
+    measures the capacity itself); latency = completion - arrival."""
     jobs = wl.config5_jobs(n_jobs=n_jobs)
     T = np.array([j.n_trials for j in jobs], dtype=np.float64)
-    rate = load * capacity_trials_per_s / T.mean()
-    arrivals = wl.poisson_arrivals(len(jobs), rate)
+    if load > 0:
+        rate = load * capacity_trials_per_s / T.mean()
+        arrivals = wl.poisson_arrivals(len(jobs), rate)
+    else:
+        rate = float("inf")
+        arrivals = np.zeros(len(jobs))
     res = {}
     with pb.Server(hbm_budget_bytes=budget_mb << 20, max_slots=1024, steps_per_round=256) as srv:
         t0 = time.perf_counter()
@@ -152,12 +249,20 @@ def serve(pb, wl, n_jobs, capacity_trials_per_s, load, budget_mb):
     wait = (adm - sub) / 1e6
     trials = sum(r[2]["trials"] for r in res.values())
     span = (fin.max() - sub.min()) / 1e9
-    return {"jobs": len(jobs), "offered_jobs_per_s": rate, "offered_load": load,
+    # where the tail goes: the jobs at or above the 99th latency percentile
+    p99 = np.percentile(lat, 99)
+    order = [i for i in np.argsort(-lat) if lat[i] >= p99][:20]
+    tail = [{"sites": int(jobs[i].N), "trials": int(jobs[i].n_trials),
+             "lattice": "FCC" if jobs[i].lattice == 0 else "BCC",
+             "wait_ms": float(wait[i]), "service_ms": float((fin[i] - adm[i]) / 1e6),
+             "latency_ms": float(lat[i])} for i in order]
+    return {"jobs": len(jobs), "offered_jobs_per_s": rate if np.isfinite(rate) else None, "offered_load": load,
             "capacity_trials_per_s": capacity_trials_per_s, "hbm_budget_MB": budget_mb,
             "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
             "latency_ms_max": float(lat.max()), "admission_wait_ms_p50": float(np.percentile(wait, 50)),
             "admission_wait_ms_p99": float(np.percentile(wait, 99)), "trials": int(trials), "span_s": span,
-            "trials_per_s": trials / span, "rounds": c["rounds"], "sites_total": int(sum(j.N for j in jobs))}
+            "trials_per_s": trials / span, "rounds": c["rounds"], "sites_total": int(sum(j.N for j in jobs)),
+            "p99_tail_jobs": tail}
 
 
 def global_search(pb, p, torch):
@@ -254,6 +359,15 @@ def main():
     log = torch.zeros((p.n_trials, 4), dtype=torch.int32, device="cuda")
     par = pb.make_params(p.seed, p.chain_id, p.n_trials, p.B)
 
+    p1 = wl.config1()
+    chain1_0 = torch.from_numpy(p1.species).cuda()
+    chain1 = chain1_0.clone()
+    par1 = pb.make_params(p1.seed, p1.chain_id, p1.n_trials, p1.B)
+    p3c = wl.config3()
+    chain3_0 = torch.from_numpy(p3c.species).cuda()
+    chain3 = chain3_0.clone()
+    par3 = pb.make_params(p3c.seed, p3c.chain_id, p3c.n_trials, p3c.B)
+
     chains = wl.config4(n_chains=args.chains)
     bspecies0 = torch.from_numpy(np.concatenate([c.species for c in chains])).cuda()
     bspecies = bspecies0.clone()
@@ -279,8 +393,10 @@ def main():
     copy_dst = torch.empty_like(eval_in) if "copy" in legs else None
 
     def step(ev):
-        if "copy" in legs:   # plain copy of the evaluation batch: counter calibration
+        if "copy" in legs:   # plain copy of the evaluation batch: achievable HBM, counter calibration
+            ev["copy0"].record(stream)
             copy_dst.copy_(eval_in)
+            ev["copy1"].record(stream)
         if "eval" in legs:
             ev["eval0"].record(stream)
             pb.pyhea_sro_eval_batch(p.lattice, p.L, M, S, eval_in, counts, p.target, p.weight, S_F)
@@ -301,17 +417,32 @@ def main():
             st, _ = pb.pyhea_mc_run(p.lattice, p.L, M, S, p.target, p.weight, chain, par, log)
             ev["chain1"].record(stream)
             ev["chain_stats"] = st
+        if "chain1" in legs:
+            chain1.copy_(chain1_0)
+            ev["c1_0"].record(stream)
+            st, _ = pb.pyhea_mc_run(p1.lattice, p1.L, p1.M, p1.S, p1.target, p1.weight, chain1, par1, None)
+            ev["c1_1"].record(stream)
+            ev["chain1_stats"] = st
+        if "chain3" in legs:
+            chain3.copy_(chain3_0)
+            ev["c3_0"].record(stream)
+            st, _ = pb.pyhea_mc_run(p3c.lattice, p3c.L, p3c.M, p3c.S, p3c.target, p3c.weight, chain3, par3, None)
+            ev["c3_1"].record(stream)
+            ev["chain3_stats"] = st
         if "batch" in legs:
             bspecies.copy_(bspecies0)
             ev["batch0"].record(stream)
             ev["batch_stats"] = pb.pyhea_mc_batch(bprobs, bspecies, boff, bpars)
             ev["batch1"].record(stream)
 
-    names = ["eval0", "eval1", "eval30", "eval31", "lat0", "lat1", "chain0", "chain1", "batch0", "batch1"]
+    progress("inputs resident; warm-up")
+    names = ["eval0", "eval1", "eval30", "eval31", "lat0", "lat1", "chain0", "chain1", "batch0", "batch1",
+             "c1_0", "c1_1", "c3_0", "c3_1", "copy0", "copy1"]
     for _ in range(args.warmup):
         step({n: torch.cuda.Event(enable_timing=True) for n in names})
     torch.cuda.synchronize()
     evs = [{n: torch.cuda.Event(enable_timing=True) for n in names} for _ in range(args.steps)]
+    progress(f"{args.steps} timed steps")
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(evs[i])
@@ -346,6 +477,27 @@ def main():
             "valu_lane_ops_per_trial": lane_ops,
             "valu_frac_chip": None if lane_ops is None else tps * lane_ops / VALU_LANE_OPS_PEAK,
             "valu_frac_one_cu": None if lane_ops is None else tps * lane_ops / (VALU_LANE_OPS_PEAK / 256)}
+    for leg, (a, b), pp, key, lanes_key in (("chain1", ("c1_0", "c1_1"), p1, "chain_fcc4", "fcc4"),
+                                             ("chain3", ("c3_0", "c3_1"), p3c, "chain_fcc40", "fcc40")):
+        if leg not in legs:
+            continue
+        ms = np.array(leg_ms(a, b))
+        st = evs[-1][leg + "_stats"]
+        tps = pp.n_trials / (ms.mean() / 1e3)
+        zsum = {0: [12, 6, 24, 12], 1: [8, 6, 12, 24]}[pp.lattice][:pp.S]
+        gathered = 2 * (1 + sum(zsum))
+        out[key] = {"trials_per_s": tps, "ms": float(ms.mean()), "trials": st["trials"],
+                    "commits": st["commits"], "final_F": st["F"],
+                    "workload": f"FCC {pp.L[0]}^3 ({pp.N} sites), {pp.M} species, shells 1-{pp.S}, "
+                                f"{pp.n_trials} trials, B={pp.B}, disjoint commits",
+                    "roofline_chain": {"bound": "latency", "gathered_bytes_per_trial": gathered,
+                                       "hbm_frac": tps * gathered / (HBM_PEAK_GBPS * 1e9)}}
+    if "copy" in legs:
+        ms = np.array(leg_ms("copy0", "copy1"))
+        moved = 2 * eval_in.numel()   # read + write
+        out["achievable_hbm"] = {"GBps": moved / (ms.mean() / 1e3) / 1e9, "ms": float(ms.mean()),
+                                 "bytes_read_plus_written": moved,
+                                 "what": "torch copy_ of the 1.05 GB evaluation batch (HIP copy kernel)"}
     if "eval" in legs:
         ms = np.array(leg_ms("eval0", "eval1"))
         alg_bytes = K * (N + S * M * M * 4 + 16)
@@ -382,6 +534,7 @@ def main():
         if "chain" in legs:
             out["batched"]["vs_fcc20_chain"] = out["batched"]["trials_per_s"] / out["value"]
         if not args.no_plain:
+            progress("plain chains one after another")
             # the same chains one after another through the single-chain entry point
             batched_final = bspecies.clone()
             bspecies.copy_(bspecies0)
@@ -402,22 +555,32 @@ def main():
                 print("batched and plain chains ended in different configurations", file=sys.stderr)
                 sys.exit(1)
     if args.serve_jobs > 0:
-        cap = out.get("batched", {}).get("trials_per_s", 1.0e9)
-        out["serving"] = serve(pb, wl, args.serve_jobs, cap, args.serve_load, args.serve_budget_mb)
-        out["serving"]["capacity_source"] = "512 batched chains (C4) of this run"
-        # the C5 jobs are heavier than the C4 chains, so that load overruns the
-        # server; the same jobs again at 70 % of the aggregate rate it served
-        cap2 = out["serving"]["trials_per_s"]
-        out["serving_steady"] = serve(pb, wl, args.serve_jobs, cap2, args.serve_load, args.serve_budget_mb)
-        out["serving_steady"]["capacity_source"] = "aggregate rate of the first serving run"
+        progress("serving: capacity run")
+        # capacity of the server on this job mix: every job submitted at once
+        probe = serve(pb, wl, args.serve_jobs, 0.0, 0.0, args.serve_budget_mb)
+        out["serving_capacity"] = {k: probe[k] for k in ("jobs", "trials", "span_s", "trials_per_s", "rounds")}
+        out["serving_capacity"]["what"] = "all jobs submitted at t = 0 (saturated server)"
+        progress("serving: Poisson arrivals")
+        # Poisson arrivals at a fraction of that capacity: latency of a server that keeps up
+        out["serving"] = serve(pb, wl, args.serve_jobs, probe["trials_per_s"], args.serve_load, args.serve_budget_mb)
+        out["serving"]["capacity_source"] = "saturated run of the same job mix (serving_capacity)"
+    if not args.no_best and "chain" in legs:
+        progress("BEST vs DISJOINT")
+        out["best_vs_disjoint"] = best_vs_disjoint(pb, p, torch, p.n_trials / out["value"], out["chain"]["final_F"])
     if not args.no_global:
+        progress("global search")
         out["global_search"] = global_search(pb, p, torch)
     if not args.no_baseline:
+        progress("incremental vs full")
         out["incremental_vs_full"] = incremental_vs_full(pb, p, torch, out)
     if "value" not in out:
         out["value"] = None
     if not args.no_cpu_baseline:
+        progress("oracle on the host")
         out["cpu_baseline"] = cpu_baseline(p)
+        if not args.no_cpu_batch and "batch" in legs:
+            out["cpu_baseline_batched"] = cpu_batch_baseline(chains)
+            out["cpu_baseline_batched"]["gpu_batched_trials_per_s"] = out["batched"]["trials_per_s"]
     print(json.dumps(out))
 
 
