@@ -20,7 +20,11 @@ struct BitDesc {
     int32_t nchunks;   // workgroups per configuration
     int32_t threads;   // workgroup size
     int32_t partial_stride;
-    uint32_t N;
+    uint32_t N;          // sites of the configuration the kernel counts
+    uint32_t cfg_stride; // bytes per configuration in the batch
+    int32_t dbl;         // BCC with an odd number of cells along x, counted as
+                         // the configuration repeated twice along x (N = 2 x
+                         // the original's sites; counts are halved on output)
     int32_t nh;
     int32_t hstart[kMaxShells + 1];
     int32_t zk[kMaxShells];
@@ -43,6 +47,7 @@ struct StreamDesc {
     int32_t threads;
     int32_t maxd;           // load blocks per lane the kernel holds offsets for
     int32_t grid;           // persistent workgroups
+    int32_t dbl;            // always 0 (the doubled BCC layout is the bit-sliced kernel's)
     uint32_t N;
     int32_t zk[kMaxShells];
     int32_t hs[4][2][kMaxShells + 1];   // per basis and layer step dz: start of shell k's half offsets
@@ -58,8 +63,9 @@ hipError_t launch_count_stream(const Geometry &g, const StreamDesc &sd, int64_t 
                                int32_t *counts, int32_t *bad, const double *tw, double *S_F, hipStream_t stream);
 
 // Fills bd; false if the bit-sliced kernel does not cover this geometry (it
-// covers FCC, and BCC with an even number of cells along x, for shells whose
-// neighbours lie at most one cell away).
+// covers FCC and BCC for shells whose neighbours lie at most one cell away;
+// a BCC cell with an odd number of cells along x is counted as itself repeated
+// twice along x, whose pair counts are exactly twice its own).
 // K is the number of configurations of the launch: few configurations are
 // split along z over more workgroups.  With split > 1, a configuration whose
 // layers would take more than 1/split of a CU's LDS is cut along z so that

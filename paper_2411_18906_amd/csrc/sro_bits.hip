@@ -106,7 +106,7 @@ __device__ __forceinline__ void epilogue(const int32_t *pairs, const Desc &bd, i
     }
     __syncthreads();
     for (int e = tid; e < S * M * M; e += blockDim.x) {
-        cnt[e] = lc[e];
+        cnt[e] = bd.dbl ? lc[e] / 2 : lc[e];   // a doubled layout counts every pair twice
         if (S_F) {
             const int k = e / (M * M), i = (e / M) % M, j = e % M;
             const double R = (double)bd.N / (double)(n[i] * n[j] * (int64_t)bd.zk[k]);
@@ -316,7 +316,7 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
     __syncthreads();
 
     // ---- 1. conversion: one padded row (layer ll, row fy) per item ------------------
-    const uint8_t *cfg = reinterpret_cast<const uint8_t *>(species) + kc * (int64_t)bd.N;
+    const uint8_t *cfg = reinterpret_cast<const uint8_t *>(species) + kc * (int64_t)bd.cfg_stride;
     uint32_t badacc = 0;
     const uint32_t kBad = (0x80u - M) * 0x01010101u;   // byte + kBad has bit 7 set iff byte >= M (bytes < 0x80)
     const int rows = bd.Ly + 2;
@@ -401,7 +401,17 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
                     for (int m = 0; m < 8; ++m) {
                         int c = 32 * cxc + 8 * g + m - 1;
                         c = c < 0 ? bd.Lx - 1 : (c >= bd.Lx ? 0 : c);
-                        d[gg][m] = *reinterpret_cast<const uint32_t *>(cfg + (rowoff + 4u * (uint32_t)c));
+                        if (bd.dbl) {   // uniform: four-site cell c = BCC cells 2c, 2c + 1 (mod Lx) of the row
+                            const uint32_t row2 = rowoff >> 1;   // the BCC row: 2 Lx bytes
+                            int lo = 2 * c, hi = 2 * c + 1;
+                            lo = lo >= bd.Lx ? lo - bd.Lx : lo;
+                            hi = hi >= bd.Lx ? hi - bd.Lx : hi;
+                            const uint32_t a = *reinterpret_cast<const uint16_t *>(cfg + (row2 + 2u * (uint32_t)lo));
+                            const uint32_t b = *reinterpret_cast<const uint16_t *>(cfg + (row2 + 2u * (uint32_t)hi));
+                            d[gg][m] = a | (b << 16);
+                        } else {
+                            d[gg][m] = *reinterpret_cast<const uint32_t *>(cfg + (rowoff + 4u * (uint32_t)c));
+                        }
                     }
                 }
 #pragma unroll
@@ -618,6 +628,8 @@ __global__ void finalize_bits_kernel(BitDesc bd, int64_t K, const int32_t *__res
     n[M - 1] = rest;
     bad[kc] = pa[S * NP + P] ? 1 : 0;
     for (int k = 0; k < S; ++k) expand_shell<M>(pa + k * NP, bd.zk[k], n, c + k * M * M);
+    if (bd.dbl)   // a doubled layout counts every pair twice
+        for (int e = 0; e < S * M * M; ++e) c[e] /= 2;
 }
 
 // slot sums -> counts and Eq. 2-3 (one 64-thread block per configuration)
@@ -1025,7 +1037,7 @@ hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_
     for (int64_t k0 = 0; k0 < K; k0 += 65535) {
         const int64_t kn = std::min<int64_t>(65535, K - k0);
         hipLaunchKernelGGL(fn, dim3(bd.nchunks, (unsigned)kn), dim3(bd.threads), lds, stream, bd, kn,
-                           species + k0 * (int64_t)bd.N, partial + k0 * bd.nchunks * bd.partial_stride,
+                           species + k0 * (int64_t)bd.cfg_stride, partial + k0 * bd.nchunks * bd.partial_stride,
                            counts + k0 * (int64_t)(S * M * M), bad + k0, tw, S_F ? S_F + 2 * k0 : nullptr);
     }
     if (bd.nchunks > 1 && S_F)
@@ -1092,14 +1104,29 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitD
     // ((cz Ly + cy) Lx + cx) 2 + b is ((cz Ly + cy) (Lx/2) + cx/2) 4 + 2 (cx % 2) + b,
     // so an even-Lx BCC configuration is laid out as cells of four sublattices)
     int Lx4;
-    if (g.lattice == PYHEA_FCC)
+    int dbl = 0;
+    if (g.lattice == PYHEA_FCC) {
         Lx4 = g.L[0];
-    else if (g.lattice == PYHEA_BCC && g.L[0] % 2 == 0)
+    } else if (g.lattice == PYHEA_BCC && g.L[0] % 2 == 0) {
         Lx4 = g.L[0] / 2;
-    else
+    } else if (g.lattice == PYHEA_BCC) {
+        // odd Lx: the configuration repeated twice along x (2 Lx BCC cells = Lx
+        // four-site cells).  Every (site, offset) pair of the repeated cell has
+        // the species pair of its image in the original (the species pattern
+        // has period Lx), so its counts are exactly twice the original's, and
+        // alpha, S and F (Eq. 2-3) are unchanged bit for bit (N, n_i, n_j and
+        // N_ij all double: powers of two scale binary64 exactly).
+        Lx4 = g.L[0];
+        dbl = 1;
+        int zmax = 0;
+        for (int k = 0; k < g.S; ++k) zmax = std::max(zmax, g.z[k]);
+        if (2 * g.N * (int64_t)zmax >= ((int64_t)1 << 31)) return false;   // doubled counts stay int32
+    } else {
         return false;
+    }
     const int P = g.M - 1;
     bd->Lx = Lx4;
+    bd->dbl = dbl;
     bd->Ly = g.L[1];
     bd->Lz = g.L[2];
     bd->RS = Lx4 + 2;
@@ -1110,7 +1137,8 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitD
     bd->cw0 = bd->RS / 32;
     bd->NCW = ((g.L[1] + 1) * bd->RS - 1) / 32 - bd->cw0 + 1;
     bd->nchx = (bd->RS + 31) / 32;
-    bd->N = (uint32_t)g.N;
+    bd->N = (uint32_t)(dbl ? 2 * g.N : g.N);
+    bd->cfg_stride = (uint32_t)g.N;
     const int np = P * (P + 1) / 2;
     bd->partial_stride = ((g.S * np + P + 1) + 3) & ~3;
     for (int k = 0; k < kMaxShells; ++k) bd->zk[k] = k < g.S ? g.z[k] : 0;
@@ -1168,7 +1196,7 @@ hipError_t launch_count_bits(const Geometry &g, const BitDesc &bd, int64_t K, co
     LaunchFn f = pick(g.M, g.S);
     if (!f) return hipErrorInvalidValue;
     BitDesc b = bd;
-    b.vec4 = bd.Lx % 4 == 0 && (reinterpret_cast<uintptr_t>(species) & 15) == 0 ? 1 : 0;
+    b.vec4 = !bd.dbl && bd.Lx % 4 == 0 && (reinterpret_cast<uintptr_t>(species) & 15) == 0 ? 1 : 0;
     return f(b, K, species, partial, counts, bad, tw, S_F, stream);
 }
 

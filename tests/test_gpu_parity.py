@@ -88,9 +88,12 @@ BATCH_SHAPES = [
     (orc.FCC, (40, 40, 40), 4, 2, 3), (orc.FCC, (33, 5, 7), 3, 4, 4), (orc.FCC, (1, 2, 3), 2, 1, 5),
     (orc.FCC, (70, 3, 6), 6, 2, 4), (orc.FCC, (2, 2, 2), 8, 2, 6), (orc.FCC, (7, 3, 2), 7, 1, 5),
     (orc.FCC, (6, 5, 4), 6, 4, 5), (orc.FCC, (64, 64, 64), 5, 3, 3),
-    # BCC with even Lx runs on the four-site-cell layout; odd Lx and shell 4 use gathers
+    # BCC with even Lx runs on the four-site-cell layout; shell 4 uses gathers
     (orc.BCC, (8, 8, 8), 5, 3, 20), (orc.BCC, (2, 3, 3), 3, 3, 7), (orc.BCC, (10, 4, 6), 6, 2, 9),
     (orc.BCC, (64, 32, 32), 4, 2, 3), (orc.BCC, (7, 4, 4), 3, 2, 5), (orc.BCC, (4, 4, 4), 4, 4, 4),
+    # BCC with odd Lx: counted as the configuration repeated twice along x
+    (orc.BCC, (31, 31, 31), 5, 3, 3), (orc.BCC, (3, 5, 4), 6, 2, 12), (orc.BCC, (1, 3, 3), 4, 1, 6),
+    (orc.BCC, (9, 2, 7), 3, 3, 9), (orc.BCC, (33, 6, 5), 8, 2, 4),
     # counting order: a two-layer workgroup with 60-64 centre words per basis walks
     # them basis-major (padded to one wavefront), a one-layer workgroup layer-major;
     # the first three launches hold one of each
