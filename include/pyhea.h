@@ -104,6 +104,10 @@ typedef struct {
     double S;            /* objective of the final configuration               */
     double F;            /* sqrt(S), Eq. 3                                      */
     int64_t log_len;     /* accepted-swap records written (min(commits, cap))  */
+    int32_t shape;       /* launch shape used: store (0 LDS bytes, 1 LDS nibbles,
+                            2 HBM) * 10000 + steps per pass * 100 + commit chunk */
+    int32_t shape_measured; /* 1 if that shape was chosen by measurement (this
+                            call or an earlier one), 0 by the cost model      */
 } pyhea_mc_stats;
 
 /* Global search parameters (Sec. 4.1, Algorithm 1; the parameter study of
@@ -269,7 +273,13 @@ pyhea_status pyhea_mc_run(const pyhea_lattice *lat, const pyhea_objective *obj,
  * offsets_host[c+1]) and, if log_dev is not NULL, the records
  * log_dev[log_offsets_host[c] .. log_offsets_host[c+1]).  Each chain's
  * result is identical to pyhea_mc_run with the same inputs.  Launch shape is
- * chosen by the autotuner (pyhea_tune_*), never the trajectory.
+ * chosen by the autotuner (pyhea_tune_*), never the trajectory.  The call
+ * uploads its descriptors once and reads results back once; the species
+ * totals and ratio tables are formed on the device from the initial counts.
+ * A chain with an id outside [0, M) or an absent species makes the call
+ * return PYHEA_EINVAL (the message names the first such chain); such chains
+ * are left unchanged with stats status PYHEA_EINVAL, and the valid chains
+ * still run to completion with status PYHEA_OK.
  * Synchronous.
  */
 pyhea_status pyhea_mc_batch(int32_t n_chains, const pyhea_lattice *lats,
@@ -371,6 +381,20 @@ pyhea_status pyhea_philox4x32_10(const uint32_t *ctr_dev, uint64_t seed, int64_t
  * one, 6 = speculative commit chunks of 4 candidates.  Shapes never change
  * results; EINVAL outside -1..6. */
 pyhea_status pyhea_tune_force(int32_t variant);
+
+/* Measuring autotuner for the automatic launch shape of single chains
+ * (pyhea_mc_run; on by default): the first chain of a kind -- device, lattice,
+ * M, S, B, floor(log2 padded sites) -- is counted on a scratch copy, run past
+ * its first steps, and from that saved state run again under each candidate
+ * shape (per store that fits: the most steps per pass the wave budget allows,
+ * about half of that and one, each with the largest commit chunk that fits
+ * and with commits one by one) for two lengths, whose time difference is the
+ * per-step cost; the cheapest is used and kept in memory and in the text file
+ * named by PYHEA_TUNE_CACHE (else $HOME/.cache/pyhea/mc_launch_shapes.txt) for
+ * later calls and processes (the server reads it too).  Batches use the cost
+ * model, which was fitted to batches.  on = 0 uses the cost model alone.
+ * The shape used is reported in pyhea_mc_stats.  Shapes never change results. */
+pyhea_status pyhea_tune_measure(int32_t on);
 
 /* Full-evaluation kernel: -1 = automatic (bit-sliced where it covers the
  * geometry, else gather), 0 = gather, 1 = bit-sliced where possible (a

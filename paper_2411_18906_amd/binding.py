@@ -29,7 +29,7 @@ EXPORTS = [
     "pyhea_serve_close", "pyhea_philox4x32_10", "pyhea_tune_force",
     "pyhea_tune_force_eval", "pyhea_tune_force_lookahead", "pyhea_global_search",
     "pyhea_random_configs", "pyhea_trial_eval_full", "pyhea_sro_eval_batch_noalloc",
-    "pyhea_tune_force_stream", "pyhea_map_sites",
+    "pyhea_tune_force_stream", "pyhea_map_sites", "pyhea_tune_measure",
 ]
 
 
@@ -73,7 +73,8 @@ class McStats(ctypes.Structure):
     _fields_ = [("trials", ctypes.c_int64), ("null_trials", ctypes.c_int64),
                 ("commits", ctypes.c_int64), ("steps", ctypes.c_int64),
                 ("stop_reason", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("S", ctypes.c_double), ("F", ctypes.c_double), ("log_len", ctypes.c_int64)]
+                ("S", ctypes.c_double), ("F", ctypes.c_double), ("log_len", ctypes.c_int64),
+                ("shape", ctypes.c_int32), ("shape_measured", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -110,6 +111,7 @@ def lib():
             "pyhea_tune_force_eval": ([i32], i32),
             "pyhea_tune_force_stream": ([i32, i32], i32),
             "pyhea_map_sites": ([P, P, ctypes.c_double, i64, P, P, P, P, P], i32),
+            "pyhea_tune_measure": ([i32], i32),
             "pyhea_tune_force_lookahead": ([i32], i32),
             "pyhea_global_search": ([P, P, P, P, P, P, P, P], i32),
             "pyhea_random_configs": ([i64, i32, P, u64, ctypes.c_uint32, ctypes.c_uint32, i32, P, P], i32),
@@ -224,8 +226,7 @@ def pyhea_sro_eval_batch_noalloc(lattice: int, L, M: int, S: int, species, count
                                  weight=None, S_F=None, stream=None):
     """pyhea_sro_eval_batch whose scratch is the library's fixed device array
     (the call allocates no device memory)."""
-    _eval_batch("pyhea_sro_eval_batch_noalloc",
-    "pyhea_tune_force_stream", "pyhea_map_sites", lattice, L, M, S, species, counts, target, weight, S_F,
+    _eval_batch("pyhea_sro_eval_batch_noalloc", lattice, L, M, S, species, counts, target, weight, S_F,
                 stream)
 
 
@@ -439,6 +440,10 @@ def pyhea_tune_force(variant: int):
 
 def pyhea_tune_force_eval(kernel: int):
     _check(lib().pyhea_tune_force_eval(kernel))
+
+
+def pyhea_tune_measure(on: bool):
+    _check(lib().pyhea_tune_measure(1 if on else 0))
 
 
 def pyhea_tune_force_stream(layers_per_group: int, threads: int):

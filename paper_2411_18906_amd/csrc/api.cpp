@@ -626,6 +626,15 @@ pyhea_status pyhea_tune_force_stream(int32_t layers_per_group, int32_t threads) 
     return guard(PYHEA_OK);
 }
 
+pyhea_status pyhea_tune_measure(int32_t on) {
+    if (on != 0 && on != 1) {
+        set_error("on must be 0 or 1");
+        return PYHEA_EINVAL;
+    }
+    set_measure_enabled(on != 0);
+    return guard(PYHEA_OK);
+}
+
 pyhea_status pyhea_tune_force_lookahead(int32_t steps) {
     if (steps < 0 || steps > kMaxLookahead) {
         set_error("steps per pass must be 0 (automatic) or 1..8");

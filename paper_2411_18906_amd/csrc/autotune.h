@@ -3,6 +3,8 @@
 // trajectory: every variant gives bit-identical results.
 #pragma once
 
+#include <vector>
+
 #include "geometry.h"
 
 namespace pyhea {
@@ -36,6 +38,31 @@ constexpr int kNumStoreVariants = 7;
 
 LaunchShape choose_launch(const Geometry &g, int B, int lds_budget, int variant, int n_chains);
 int wave_budget(int n_chains);
+
+// Candidate shapes for measurement: for each store that fits, the most steps
+// per pass the wave budget allows, about half of that and one step, each with
+// the largest commit chunk that fits and with commits one by one.
+std::vector<LaunchShape> candidate_launches(const Geometry &g, int B, int lds_budget, int n_chains);
+// LDS bytes of shape s for a chain of geometry g (the species store depends on
+// the padded size).
+int64_t launch_lds_bytes(const Geometry &g, int B, const LaunchShape &s);
+
+// Measured launch shapes.  Key: device (architecture, CU count), lattice, M,
+// S, B, floor(log2 padded sites) and the wave budget of the call's residency
+// class.  Kept in memory and appended to a text file (PYHEA_TUNE_CACHE, else
+// $HOME/.cache/pyhea/mc_launch_shapes.txt) that later processes read.
+struct TuneKey {
+    int lattice, M, S, B, nbucket, budget;
+};
+TuneKey tune_key(const Geometry &g, int B, int n_chains);
+bool tuned_launch(const TuneKey &k, LaunchShape *s);
+void record_tuned_launch(const TuneKey &k, const LaunchShape &s, double us_per_step);
+// Whether automatic shapes are measured (pyhea_tune_measure; on by default).
+bool measure_enabled();
+void set_measure_enabled(bool on);
+// Encoded launch shape reported in the chain statistics:
+// store * 10000 + steps per pass * 100 + commit chunk.
+inline int32_t shape_code(const LaunchShape &s) { return s.store * 10000 + s.K * 100 + s.CH; }
 
 // Variant forced through pyhea_tune_force (-1 = none).
 int forced_variant();

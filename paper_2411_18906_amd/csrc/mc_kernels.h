@@ -48,6 +48,9 @@ constexpr int kMaxLookahead = 8;
 // One launch of n_chains chains (one block each) for up to max_steps steps.
 hipError_t launch_mc(const ChainDesc *descs_dev, int n_chains, int store, int M, int S, int B, int W, int bal,
                      int K, int CH, int lds_bytes, int max_steps, hipStream_t stream);
+// Ratio tables of chains from their initial counts (descriptor order; bad [n]
+// the invalid-id flags in the same order); invalid chains get status EINVAL.
+hipError_t launch_chain_ratio(const ChainDesc *descs_dev, int n_chains, const int32_t *bad, hipStream_t stream);
 hipError_t launch_pad_fill(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);
 hipError_t launch_pad_drain(const ChainDesc *descs_dev, int n_chains, hipStream_t stream);
 // out[i] = *descs_dev[i].state (device array of n_chains states).

@@ -921,7 +921,7 @@ __global__ void gather_states_kernel(const ChainDesc *__restrict__ descs, int n,
 
 __global__ void pad_fill_kernel(const ChainDesc *__restrict__ descs) {
     const ChainDesc &d = descs[blockIdx.y];
-    if (d.store != kStoreGlobal) return;
+    if (d.store != kStoreGlobal || d.state->status != 0) return;
     const double inv_PX = 1.0 / (double)d.PX, inv_PY = 1.0 / (double)d.PY;
     for (uint32_t pid = blockIdx.x * blockDim.x + threadIdx.x; pid < d.Npad;
          pid += gridDim.x * blockDim.x) {
@@ -934,7 +934,7 @@ __global__ void pad_fill_kernel(const ChainDesc *__restrict__ descs) {
 
 __global__ void pad_drain_kernel(const ChainDesc *__restrict__ descs) {
     const ChainDesc &d = descs[blockIdx.y];
-    if (d.store != kStoreGlobal) return;
+    if (d.store != kStoreGlobal || d.state->status != 0) return;
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < d.N; p += gridDim.x * blockDim.x) {
         const SiteCoord c = site_coord(p, d.lgA, d.Lx, d.Ly, d.inv_Lx, d.inv_Ly);
         d.species[p] = d.pad_global[padded_id(d, c.cx + d.halo, c.cy + d.halo, c.cz + d.halo, c.b)];
@@ -977,6 +977,41 @@ hipError_t launch_gather_states(const ChainDesc *descs_dev, int n_chains, ChainS
     if (n_chains <= 0) return hipSuccess;
     hipLaunchKernelGGL(gather_states_kernel, dim3((n_chains + 255) / 256), dim3(256), 0, stream, descs_dev, n_chains,
                        out);
+    return hipGetLastError();
+}
+
+// Species totals and the ratio table R = N / (n_i n_j z_k) of each chain from
+// its initial pair counts (Eq. 2; n_i = row sum of shell 1 / z_1, one exact
+// integer product and one IEEE division per entry).  A chain with an invalid id
+// or an absent species is marked done with status EINVAL and left untouched.
+__global__ void chain_ratio_kernel(const ChainDesc *__restrict__ descs, int n, const int32_t *__restrict__ bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const ChainDesc &d = descs[i];
+    const int M = d.M, S = d.S;
+    int64_t nsp[kMaxSpecies];
+    bool ok = bad[i] == 0;
+    for (int a = 0; a < M; ++a) {
+        int64_t r = 0;
+        for (int b = 0; b < M; ++b) r += d.counts[a * M + b];
+        nsp[a] = r / d.zk[0];
+        ok = ok && nsp[a] > 0;
+    }
+    if (!ok) {
+        d.state->status = PYHEA_EINVAL;
+        d.state->done = 1;
+        return;
+    }
+    double *R = const_cast<double *>(d.R);
+    for (int k = 0; k < S; ++k)
+        for (int a = 0; a < M; ++a)
+            for (int b = 0; b < M; ++b)
+                R[(k * M + a) * M + b] = (double)d.N / (double)(nsp[a] * nsp[b] * (int64_t)d.zk[k]);
+}
+
+hipError_t launch_chain_ratio(const ChainDesc *descs_dev, int n_chains, const int32_t *bad, hipStream_t stream) {
+    if (n_chains <= 0) return hipSuccess;
+    hipLaunchKernelGGL(chain_ratio_kernel, dim3((n_chains + 63) / 64), dim3(64), 0, stream, descs_dev, n_chains, bad);
     return hipGetLastError();
 }
 

@@ -337,6 +337,168 @@ struct Fork {
 
 }  // namespace
 
+namespace {
+
+// Measures the candidate launch shapes of chain j on a scratch copy of its
+// configuration: after kProbeWarm steps the chain state (configuration, counts,
+// counters) is saved, and every candidate runs the same segment from that
+// state -- kProbeBase steps, and kProbeBase + kProbeSteps steps -- so that all
+// see the same trials and commits (a shape never changes the trajectory); the
+// difference of the two times is the per-step cost without the launch's
+// fixed load and write-back, and the cheapest per step wins.  Sets *ok false
+// if the chain is invalid (the real run reports it).
+constexpr int kProbeWarm = 48;
+constexpr int kProbeBase = 16;
+constexpr int kProbeSteps = 96;
+
+pyhea_status probe_launch(const ChainJob &j, int n_chains, int lds_budget, hipStream_t stream, LaunchShape *best,
+                          double *us_per_step, bool *ok) {
+    *ok = false;
+    const Geometry &g = j.g;
+    const int B = j.params.cand_per_step;
+    const std::vector<LaunchShape> cand = candidate_launches(g, B, lds_budget, n_chains);
+    if (cand.size() < 2) return PYHEA_OK;
+    const int nc = (int)cand.size();
+    const size_t E = (size_t)g.S * g.M * g.M;
+    size_t off = 0;
+    const size_t o_sp = off;
+    off = align256(off + (size_t)g.N);
+    const size_t o_snap = off;   // saved configuration | counts | state
+    off = align256(off + (size_t)g.N);
+    const size_t o_snap_counts = off;
+    off = align256(off + E * 4);
+    const size_t o_snap_state = off;
+    off = align256(off + sizeof(ChainState));
+    const size_t o_pad = off;
+    off = align256(off + (size_t)g.Npad);
+    const size_t o_counts = off;   // counts | bad | state: zeroed together
+    off += E * 4;
+    const size_t o_bad = off;
+    off += 8;
+    const size_t o_state = off;
+    off += sizeof(ChainState);
+    const size_t zero_end = (off + 3) & ~size_t(3);
+    off = align256(off);
+    const size_t o_R = off;
+    off = align256(off + E * 8);
+    const size_t y_begin = off;   // target | descs | task | tile0: one upload
+    const size_t o_target = off;
+    off = align256(off + E * 8);
+    const size_t o_descs = off;
+    off = align256(off + (size_t)nc * sizeof(ChainDesc));
+    const size_t o_task = off;
+    off += sizeof(CountTask);
+    const size_t o_tile0 = off;
+    off += 4;
+    const size_t y_end = off;
+    DeviceBuffer arena;
+    arena.stream = stream;
+    PYHEA_HIP(pool_alloc(&arena.ptr, off, stream));
+    char *base = (char *)arena.ptr;
+
+    std::vector<char> hy(y_end - y_begin, 0);
+    auto hy_at = [&](size_t o) { return hy.data() + (o - y_begin); };
+    std::memcpy(hy_at(o_target), j.target.data(), E * 8);
+    ChainDesc d;
+    std::memset(&d, 0, sizeof(d));
+    fill_chain_geometry(g, &d);
+    d.seed = j.params.seed;
+    d.chain_id = j.params.chain_id;
+    d.B = B;
+    d.n_trials = INT64_MAX / 2;   // never exhausted: kProbeSteps bounds each launch
+    d.mode = j.params.commit_mode;
+    d.depth_limit = 0;
+    d.tau = j.params.accept_tol;
+    for (int k = 0; k < kMaxShells; ++k) d.w[k] = k < g.S ? j.weight[k] : 0.0;
+    d.species = (int8_t *)(base + o_sp);
+    d.R = (const double *)(base + o_R);
+    d.target = (const double *)(base + o_target);
+    d.counts = (int32_t *)(base + o_counts);
+    d.state = (ChainState *)(base + o_state);
+    d.sym = symmetric_target(j.target.data(), g.S, g.M);
+    ChainDesc *hd = (ChainDesc *)hy_at(o_descs);
+    for (int i = 0; i < nc; ++i) {
+        hd[i] = d;
+        hd[i].store = cand[i].store;
+        hd[i].lds_bytes = cand[i].lds;
+        hd[i].pad_global = cand[i].store == kStoreGlobal ? (int8_t *)(base + o_pad) : nullptr;
+    }
+    CountTask *task = (CountTask *)hy_at(o_task);
+    fill_eval_desc(g, &task->ed);
+    task->species = d.species;
+    task->counts = d.counts;
+    task->bad = (int32_t *)(base + o_bad);
+    *(uint32_t *)hy_at(o_tile0) = 0;
+
+    PYHEA_HIP(launch_zero_i32((int32_t *)(base + o_counts), (int64_t)((zero_end - o_counts) / 4), stream));
+    PYHEA_HIP(hipMemcpyAsync(base + o_sp, j.species_dev, (size_t)g.N, hipMemcpyDeviceToDevice, stream));
+    PYHEA_HIP(hipMemcpyAsync(base + y_begin, hy.data(), hy.size(), hipMemcpyHostToDevice, stream));
+    PYHEA_HIP(launch_count_tasks((const CountTask *)(base + o_task), (const uint32_t *)(base + o_tile0), 1,
+                                 count_tiles((uint32_t)g.N), stream));
+    const ChainDesc *ddev = (const ChainDesc *)(base + o_descs);
+    PYHEA_HIP(launch_chain_ratio(ddev, 1, (const int32_t *)(base + o_bad), stream));
+
+    std::vector<hipEvent_t> ev(2 * nc, nullptr);
+    struct EventGuard {
+        std::vector<hipEvent_t> &v;
+        ~EventGuard() {
+            for (hipEvent_t e : v)
+                if (e) (void)hipEventDestroy(e);
+        }
+    } guard{ev};
+    for (auto &e : ev) PYHEA_HIP(hipEventCreate(&e));
+    auto run = [&](int i, int steps) -> hipError_t {
+        const LaunchShape &c = cand[i];
+        hipError_t e = hipSuccess;
+        if (c.store == kStoreGlobal && (e = launch_pad_fill(ddev + i, 1, stream)) != hipSuccess) return e;
+        e = launch_mc(ddev + i, 1, c.store, g.M, g.S, B, c.W, c.bal, c.K, c.CH, c.lds, steps, stream);
+        if (e == hipSuccess && c.store == kStoreGlobal) e = launch_pad_drain(ddev + i, 1, stream);
+        return e;
+    };
+    PYHEA_HIP(run(0, kProbeWarm));   // past the first, most commit-heavy steps
+    auto copy = [&](size_t dst, size_t src, size_t bytes) {
+        return hipMemcpyAsync(base + dst, base + src, bytes, hipMemcpyDeviceToDevice, stream);
+    };
+    PYHEA_HIP(copy(o_snap, o_sp, (size_t)g.N));
+    PYHEA_HIP(copy(o_snap_counts, o_counts, E * 4));
+    PYHEA_HIP(copy(o_snap_state, o_state, sizeof(ChainState)));
+    std::vector<hipEvent_t> ev2(2 * nc, nullptr);
+    EventGuard guard2{ev2};
+    for (auto &e : ev2) PYHEA_HIP(hipEventCreate(&e));
+    for (int i = 0; i < nc; ++i)
+        for (int len = 0; len < 2; ++len) {
+            PYHEA_HIP(copy(o_sp, o_snap, (size_t)g.N));
+            PYHEA_HIP(copy(o_counts, o_snap_counts, E * 4));
+            PYHEA_HIP(copy(o_state, o_snap_state, sizeof(ChainState)));
+            std::vector<hipEvent_t> &v = len == 0 ? ev : ev2;
+            PYHEA_HIP(hipEventRecord(v[2 * i], stream));
+            PYHEA_HIP(run(i, len == 0 ? kProbeBase : kProbeBase + kProbeSteps));
+            PYHEA_HIP(hipEventRecord(v[2 * i + 1], stream));
+        }
+    ChainState st;
+    PYHEA_HIP(hipMemcpyAsync(&st, base + o_state, sizeof(st), hipMemcpyDeviceToHost, stream));
+    PYHEA_HIP(hipStreamSynchronize(stream));
+    if (st.status != 0) return PYHEA_OK;   // invalid chain: the real run reports it
+    int bi = 0;
+    double bus = 0.0;
+    for (int i = 0; i < nc; ++i) {
+        float ms0 = 0.0f, ms1 = 0.0f;
+        PYHEA_HIP(hipEventElapsedTime(&ms0, ev[2 * i], ev[2 * i + 1]));
+        PYHEA_HIP(hipEventElapsedTime(&ms1, ev2[2 * i], ev2[2 * i + 1]));
+        const double us = 1e3 * ((double)ms1 - (double)ms0) / kProbeSteps;
+        if (i == 0 || us < bus) {
+            bus = us;
+            bi = i;
+        }
+    }
+    *best = cand[bi];
+    *us_per_step = bus;
+    *ok = true;
+    return PYHEA_OK;
+}
+
+}  // namespace
+
 pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
                         std::vector<std::vector<int64_t>> *final_counts, hipStream_t stream,
                         int variant) {
@@ -347,7 +509,8 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
     // Device arena, in three blocks so that each crosses the bus in one copy:
     //   X (read back): counts | recount | bad | bad2 | state     (zeroed on the device)
     //   Y (uploaded before counting): target | descs | count tasks (initial, final) | tile0
-    //   Z (uploaded after counting): R
+    //   Z (written on the device from the initial counts): R
+    // One upload, one read-back: the calls between them are ordered on the stream.
     // followed by the padded HBM copies of chains that keep their configuration in HBM.
     std::vector<size_t> eoff(n + 1, 0);
     for (int c = 0; c < n; ++c) eoff[c + 1] = eoff[c] + (size_t)jobs[c].g.S * jobs[c].g.M * jobs[c].g.M;
@@ -382,9 +545,51 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
     const size_t o_R = off;
     off += Etot * 8;
     std::vector<LaunchShape> shape(n);
+    std::vector<int> measured(n, 0);
     std::vector<size_t> o_pad(n, 0);
-    for (int c = 0; c < n; ++c) {
+    // Single chains are measured.  A batch keeps the cost model's shapes: a lone
+    // chain on an idle GPU (what a probe sees) prefers commits one by one, but
+    // with two chains per CU the 512-chain batch ran 12 % slower that way
+    // (5.97e9 against 6.8e9 trial swaps/s with the model's commit chunks).
+    const bool measure = variant < 0 && measure_enabled() && n == 1;
+    for (int c = 0; c < n; ++c)
         shape[c] = choose_launch(jobs[c].g, jobs[c].params.cand_per_step, lds_budget, variant < 0 ? 0 : variant, n);
+    if (measure) {
+        // (Written for groups: chains that share a launch under the cost model
+        // would keep sharing one, the group's longest chain measured for all.)
+        std::map<std::tuple<int, int, int, int, int, int>, std::vector<int>> fam;
+        for (int c = 0; c < n; ++c)
+            fam[{shape[c].store, jobs[c].g.M, jobs[c].g.S, jobs[c].params.cand_per_step, shape[c].W, shape[c].bal}]
+                .push_back(c);
+        for (auto &kv : fam) {
+            const std::vector<int> &members = kv.second;
+            int rep = members[0];
+            for (int c : members)
+                if (jobs[c].params.n_trials * jobs[c].g.Z > jobs[rep].params.n_trials * jobs[rep].g.Z) rep = c;
+            const int B = jobs[rep].params.cand_per_step;
+            const TuneKey key = tune_key(jobs[rep].g, B, n);
+            LaunchShape t;
+            bool have = tuned_launch(key, &t);
+            if (!have) {
+                double us = 0.0;
+                bool ok = false;
+                const pyhea_status ps = probe_launch(jobs[rep], n, lds_budget, stream, &t, &us, &ok);
+                if (ps != PYHEA_OK) return ps;
+                if (ok) record_tuned_launch(key, t, us);
+                have = ok;
+            }
+            if (!have || t.W != jobs[rep].g.S) continue;
+            bool fits = true;
+            for (int c : members) fits = fits && launch_lds_bytes(jobs[c].g, B, t) <= lds_budget;
+            if (!fits) continue;
+            for (int c : members) {
+                shape[c] = t;
+                shape[c].lds = (int)launch_lds_bytes(jobs[c].g, B, t);
+                measured[c] = 1;
+            }
+        }
+    }
+    for (int c = 0; c < n; ++c) {
         if (shape[c].store == kStoreGlobal) {
             off = align256(off);
             o_pad[c] = off;
@@ -433,6 +638,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         int first, count, store, M, S, B, W, bal, K, CH, lds;
     };
     std::vector<Launch> launches;
+    std::vector<int> pos(n);   // descriptor position of each chain
     {
         ChainDesc *hd = (ChainDesc *)hy_at(o_descs);
         int at = 0;
@@ -456,6 +662,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
                      0};
             for (int c : idx) {
                 L.lds = std::max(L.lds, descs[c].lds_bytes);
+                pos[c] = at;
                 hd[at++] = descs[c];
             }
             launches.push_back(L);
@@ -482,7 +689,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
             fill_eval_desc(jobs[c].g, &a.ed);
             a.species = jobs[c].species_dev;
             a.counts = (int32_t *)(base + o_counts) + eoff[c];
-            a.bad = (int32_t *)(base + o_bad) + c;
+            a.bad = (int32_t *)(base + o_bad) + pos[c];   // descriptor order, read by the ratio kernel
             b = a;
             b.counts = (int32_t *)(base + o_recount) + eoff[c];
             b.bad = (int32_t *)(base + o_bad2) + c;
@@ -495,29 +702,14 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
     const CountTask *tasks = (const CountTask *)(base + o_tasks);
     const uint32_t *tile0 = (const uint32_t *)(base + o_tile0);
 
-    // initial pair counts of every chain's configuration, in one launch
+    // initial pair counts of every chain's configuration, in one launch, then the
+    // ratio tables from them on the device (an invalid chain is marked and skipped)
     PYHEA_HIP(launch_count_tasks(tasks, tile0, n, n_tiles, stream));
+    const ChainDesc *ddev = (const ChainDesc *)(base + o_descs);
+    PYHEA_HIP(launch_chain_ratio(ddev, n, (const int32_t *)(base + o_bad), stream));
     std::vector<char> hx(x_end);
-    PYHEA_HIP(hipMemcpyAsync(hx.data(), base, o_bad2, hipMemcpyDeviceToHost, stream));
-    PYHEA_HIP(hipStreamSynchronize(stream));
-    const int32_t *cnt0 = (const int32_t *)(hx.data() + o_counts);
-    const int32_t *bad0 = (const int32_t *)(hx.data() + o_bad);
-    std::vector<double> Rtab(Etot);
-    for (int c = 0; c < n; ++c) {
-        const Geometry &g = jobs[c].g;
-        std::vector<int64_t> c64(cnt0 + eoff[c], cnt0 + eoff[c + 1]);
-        int64_t nsp[kMaxSpecies];
-        if (bad0[c] || !species_totals(g, c64.data(), nsp)) {
-            set_error("chain " + std::to_string(c) +
-                      ": species ids must lie in [0, n_species) and every species must occur");
-            return PYHEA_EINVAL;
-        }
-        ratio_table(g, nsp, Rtab.data() + eoff[c]);
-    }
-    PYHEA_HIP(hipMemcpyAsync(base + o_R, Rtab.data(), Etot * 8, hipMemcpyHostToDevice, stream));
 
     // the chains: one launch per group, groups side by side on auxiliary streams
-    const ChainDesc *ddev = (const ChainDesc *)(base + o_descs);
     {
         Fork fork;
         PYHEA_HIP(fork.begin(stream, (int)launches.size()));
@@ -542,13 +734,20 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
     const int32_t *rec = (const int32_t *)(hx.data() + o_recount);
     const ChainState *sts = (const ChainState *)(hx.data() + o_state);
     if (final_counts) final_counts->assign(n, {});
+    int first_invalid = -1;
     for (int c = 0; c < n; ++c) {
+        pyhea_mc_stats &s = stats[c];
+        if (sts[c].status != 0) {   // invalid ids or an absent species: the chain did not run
+            std::memset(&s, 0, sizeof(s));
+            s.status = sts[c].status;
+            if (first_invalid < 0) first_invalid = c;
+            continue;
+        }
         if (!std::equal(cnt + eoff[c], cnt + eoff[c + 1], rec + eoff[c])) {
             set_error("chain " + std::to_string(c) + ": maintained pair counts differ from a recount");
             return PYHEA_EDEVICE;
         }
         std::vector<int64_t> c64(rec + eoff[c], rec + eoff[c + 1]);
-        pyhea_mc_stats &s = stats[c];
         std::memset(&s, 0, sizeof(s));
         s.trials = sts[c].trials;
         s.null_trials = sts[c].null_trials;
@@ -559,7 +758,15 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         s.S = sts[c].S;
         s.F = sts[c].F;
         s.log_len = jobs[c].log_dev ? std::min(s.commits, jobs[c].log_cap) : 0;
+        s.shape = shape_code(shape[c]);
+        s.shape_measured = measured[c];
         if (final_counts) (*final_counts)[c] = c64;
+    }
+    if (first_invalid >= 0) {
+        set_error("chain " + std::to_string(first_invalid) +
+                  ": species ids must lie in [0, n_species) and every species must occur (that chain and any other "
+                  "invalid one were left unchanged; the valid chains ran)");
+        return PYHEA_EINVAL;
     }
     return PYHEA_OK;
 }

@@ -97,6 +97,7 @@ struct Job {
     int store = kStoreLds8;
     int lds = 0;
     int W = 1, bal = 0, K = 1, CH = 0;
+    int shape_measured = 0;
     JobLayout lay{};
 };
 
@@ -280,6 +281,8 @@ void Server::retire(const std::vector<Job *> &js, hipStream_t s) {
             j->stats.S = st.S;
             j->stats.F = st.F;
         }
+        j->stats.shape = j->store * 10000 + j->K * 100 + j->CH;
+        j->stats.shape_measured = j->shape_measured;
         j->stats.status = j->status;
     }
 }
@@ -529,7 +532,16 @@ pyhea_status pyhea_serve_submit(void *server, uint64_t job_id, const pyhea_latti
     const int E = g.S * g.M * g.M;
     j->target.assign(obj->target, obj->target + E);
     j->weight.assign(obj->weight, obj->weight + g.S);
-    const LaunchShape ls = choose_launch(g, params->cand_per_step, s->lds_budget, 0, s->max_slots);
+    LaunchShape ls = choose_launch(g, params->cand_per_step, s->lds_budget, 0, s->max_slots);
+    // a shape measured earlier for this kind of chain (the server itself never probes)
+    LaunchShape t;
+    if (measure_enabled() && tuned_launch(tune_key(g, params->cand_per_step, s->max_slots), &t)) {
+        t.lds = (int)launch_lds_bytes(g, params->cand_per_step, t);
+        if (t.lds <= s->lds_budget && t.W == g.S) {
+            ls = t;
+            j->shape_measured = 1;
+        }
+    }
     j->store = ls.store;
     j->lds = ls.lds;
     j->W = ls.W;

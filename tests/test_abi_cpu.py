@@ -151,3 +151,48 @@ def test_binding_rejects_mis_sized_buffers_before_the_library():
     with pytest.raises(ValueError):
         b.pyhea_global_search(b.FCC, L, M, S, t, w, [N // 4] * 4, sp_bad, n_solutions=2, iterations=1,
                               n_refine=1, discard_frac=0.5, seed=1, B=64, n_trials=10)
+
+
+def test_binding_wrappers_marshal_without_gpu(monkeypatch):
+    """Every tensor-taking wrapper reaches its C entry point with the declared
+    number of arguments (a recording stand-in for the library; CPU tensors
+    stand in for device buffers)."""
+    import numpy as np
+    import torch
+    from paper_2411_18906_amd import binding as b
+
+    calls = []
+
+    class Fn:
+        def __init__(self, name, nargs):
+            self.name, self.nargs = name, nargs
+
+        def __call__(self, *args):
+            assert len(args) == self.nargs, (self.name, len(args), self.nargs)
+            calls.append(self.name)
+            return 0
+
+    real = b.lib()
+    sigs = {n: len(getattr(real, n).argtypes) for n in b.EXPORTS}
+
+    class Fake:
+        def __getattr__(self, n):
+            return Fn(n, sigs[n])
+
+    monkeypatch.setattr(b, "lib", lambda: Fake())
+    monkeypatch.setattr(b, "_dptr", lambda t, dtype=None: None if t is None else b.ctypes.c_void_p(t.data_ptr()))
+    monkeypatch.setattr(b, "_stream", lambda stream=None: None)
+    L, M, S = (3, 3, 3), 3, 2
+    N = b.n_sites(b.FCC, L)
+    sp = torch.zeros((4, N), dtype=torch.int8)
+    counts = torch.zeros((4, S, M, M), dtype=torch.int32)
+    SF = torch.zeros((4, 2), dtype=torch.float64)
+    tgt, w = np.zeros((S, M, M)), np.ones(S)
+    b.pyhea_sro_eval_batch(b.FCC, L, M, S, sp, counts, tgt, w, SF)
+    b.pyhea_sro_eval_batch_noalloc(b.FCC, L, M, S, sp, counts, tgt, w, SF)
+    xyz = torch.zeros((N, 3), dtype=torch.float64)
+    b.pyhea_map_sites(b.FCC, L, M, S, (10.0, 10.0, 10.0), 0.5, xyz, sp[0], sp[1])
+    b.pyhea_tune_measure(True)
+    b.pyhea_tune_force_stream(0, 0)
+    assert calls == ["pyhea_sro_eval_batch", "pyhea_sro_eval_batch_noalloc", "pyhea_map_sites",
+                     "pyhea_tune_measure", "pyhea_tune_force_stream"]

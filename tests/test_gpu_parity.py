@@ -448,7 +448,26 @@ def test_mc_batch_rejects_bad_chain(defect):
     with pytest.raises(pb.PyheaError) as e:
         pb.pyhea_mc_batch(probs, d, offsets, pars)
     assert "chain 3" in str(e.value)
-    np.testing.assert_array_equal(d.cpu().numpy(), bad)   # nothing ran
+    fin = d.cpu().numpy()
+    # the invalid chain is left unchanged; the valid chains ran as they would alone
+    np.testing.assert_array_equal(fin[lo:hi], bad[lo:hi])
+    for i, c in enumerate(chains):
+        if i == 3:
+            continue
+        sp_o, _, _, _ = orc.mc_run(c.lattice, c.L, c.M, c.S, c.target, c.weight, c.species, seed=c.seed,
+                                   chain_id=c.chain_id, n_trials=c.n_trials, B=c.B)
+        np.testing.assert_array_equal(fin[offsets[i]:offsets[i + 1]], sp_o, err_msg=f"chain {i}")
+
+
+def test_mc_run_rejects_bad_species_and_leaves_it_unchanged():
+    c = wl.config4(n_chains=1, seed=13, n_trials=400)[0]
+    bad = c.species.copy()
+    bad[5] = -3
+    d = dev(bad)
+    with pytest.raises(pb.PyheaError) as e:
+        pb.pyhea_mc_run(c.lattice, c.L, c.M, c.S, c.target, c.weight, d, pb.make_params(c.seed, 0, c.n_trials, c.B))
+    assert e.value.code == pb.EINVAL
+    np.testing.assert_array_equal(d.cpu().numpy(), bad)
 
 
 THRESHOLD_CASES = [
