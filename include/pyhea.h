@@ -388,8 +388,10 @@ pyhea_status pyhea_tune_force(int32_t variant);
  * its first steps, and from that saved state run again under each candidate
  * shape (per store that fits: the most steps per pass the wave budget allows,
  * about half of that and one, each with the largest commit chunk that fits
- * and with commits one by one) for two lengths, whose time difference is the
- * per-step cost; the cheapest is used and kept in memory and in the text file
+ * and with commits one by one, and the cost model's own shape) for two
+ * lengths, whose time difference (median of three) is the per-step cost; the
+ * cost model's shape is kept unless another is at least 3 % cheaper per step,
+ * and the choice is kept in memory and in the text file
  * named by PYHEA_TUNE_CACHE (else $HOME/.cache/pyhea/mc_launch_shapes.txt) for
  * later calls and processes (the server reads it too).  Batches use the cost
  * model, which was fitted to batches.  on = 0 uses the cost model alone.

@@ -81,13 +81,21 @@ struct CountTask {
     int32_t *counts;        // [S][M][M], zero before the launch
     int32_t *bad;           // set to 1 if a species id lies outside [0, M); zero before the launch
 };
-constexpr int kCountTile = 2048;  // sites per workgroup of the many-chain count
-inline uint32_t count_tiles(uint32_t N) { return (N + kCountTile - 1) / kCountTile; }
+// Sites per workgroup of the many-configuration count: 2048, halved (down to
+// 256) while the launch would have fewer than 2048 workgroups, so that a few
+// small configurations still spread over the chip.
+inline uint32_t count_tile_for(uint64_t total_sites) {
+    uint32_t tile = 2048;
+    while (tile > 256 && total_sites < (uint64_t)tile * 2048) tile >>= 1;
+    return tile;
+}
+inline uint32_t count_tiles(uint32_t N, uint32_t tile) { return (N + tile - 1) / tile; }
 
 // Pair counts of n configurations with different geometries in one launch.
-// tile0[c] = first tile of task c (prefix sums of count_tiles), n_tiles = total.
-hipError_t launch_count_tasks(const CountTask *tasks, const uint32_t *tile0, int n, uint32_t n_tiles,
-                              hipStream_t stream);
+// tile0[c] = first tile of task c (prefix sums of count_tiles(N, tile)),
+// n_tiles = total; max_E = the largest S M M of the tasks (LDS histograms).
+hipError_t launch_count_tasks(const CountTask *tasks, const uint32_t *tile0, int n, uint32_t n_tiles, uint32_t tile,
+                              int max_E, hipStream_t stream);
 
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t stream);
 

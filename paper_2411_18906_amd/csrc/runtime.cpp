@@ -345,18 +345,33 @@ namespace {
 // state -- kProbeBase steps, and kProbeBase + kProbeSteps steps -- so that all
 // see the same trials and commits (a shape never changes the trajectory); the
 // difference of the two times is the per-step cost without the launch's
-// fixed load and write-back, and the cheapest per step wins.  Sets *ok false
-// if the chain is invalid (the real run reports it).
+// fixed load and write-back (the median of kProbeReps such differences).  The
+// cost model's shape `model` is always a candidate, and another shape replaces
+// it only if it is at least kProbeMargin cheaper per step: shapes that differ
+// only in how commits are grouped cost the same between commits, and a short
+// segment cannot tell them apart.  Sets *ok false if the chain is invalid (the
+// real run reports it).
 constexpr int kProbeWarm = 48;
 constexpr int kProbeBase = 16;
 constexpr int kProbeSteps = 96;
+constexpr int kProbeReps = 3;
+constexpr double kProbeMargin = 0.03;
 
-pyhea_status probe_launch(const ChainJob &j, int n_chains, int lds_budget, hipStream_t stream, LaunchShape *best,
-                          double *us_per_step, bool *ok) {
+pyhea_status probe_launch(const ChainJob &j, int n_chains, int lds_budget, const LaunchShape &model,
+                          hipStream_t stream, LaunchShape *best, double *us_per_step, bool *ok) {
     *ok = false;
     const Geometry &g = j.g;
     const int B = j.params.cand_per_step;
-    const std::vector<LaunchShape> cand = candidate_launches(g, B, lds_budget, n_chains);
+    std::vector<LaunchShape> cand = candidate_launches(g, B, lds_budget, n_chains);
+    int im = -1;
+    for (int i = 0; i < (int)cand.size(); ++i)
+        if (cand[i].store == model.store && cand[i].W == model.W && cand[i].bal == model.bal && cand[i].K == model.K &&
+            cand[i].CH == model.CH)
+            im = i;
+    if (im < 0) {
+        cand.insert(cand.begin(), model);
+        im = 0;
+    }
     if (cand.size() < 2) return PYHEA_OK;
     const int nc = (int)cand.size();
     const size_t E = (size_t)g.S * g.M * g.M;
@@ -433,12 +448,16 @@ pyhea_status probe_launch(const ChainJob &j, int n_chains, int lds_budget, hipSt
     PYHEA_HIP(launch_zero_i32((int32_t *)(base + o_counts), (int64_t)((zero_end - o_counts) / 4), stream));
     PYHEA_HIP(hipMemcpyAsync(base + o_sp, j.species_dev, (size_t)g.N, hipMemcpyDeviceToDevice, stream));
     PYHEA_HIP(hipMemcpyAsync(base + y_begin, hy.data(), hy.size(), hipMemcpyHostToDevice, stream));
-    PYHEA_HIP(launch_count_tasks((const CountTask *)(base + o_task), (const uint32_t *)(base + o_tile0), 1,
-                                 count_tiles((uint32_t)g.N), stream));
+    {
+        const uint32_t tile = count_tile_for((uint64_t)g.N);
+        PYHEA_HIP(launch_count_tasks((const CountTask *)(base + o_task), (const uint32_t *)(base + o_tile0), 1,
+                                     count_tiles((uint32_t)g.N, tile), tile, (int)E, stream));
+    }
     const ChainDesc *ddev = (const ChainDesc *)(base + o_descs);
     PYHEA_HIP(launch_chain_ratio(ddev, 1, (const int32_t *)(base + o_bad), stream));
 
-    std::vector<hipEvent_t> ev(2 * nc, nullptr);
+    const int nev = 2 * nc * kProbeReps;
+    std::vector<hipEvent_t> ev(nev, nullptr);
     struct EventGuard {
         std::vector<hipEvent_t> &v;
         ~EventGuard() {
@@ -462,37 +481,45 @@ pyhea_status probe_launch(const ChainJob &j, int n_chains, int lds_budget, hipSt
     PYHEA_HIP(copy(o_snap, o_sp, (size_t)g.N));
     PYHEA_HIP(copy(o_snap_counts, o_counts, E * 4));
     PYHEA_HIP(copy(o_snap_state, o_state, sizeof(ChainState)));
-    std::vector<hipEvent_t> ev2(2 * nc, nullptr);
+    std::vector<hipEvent_t> ev2(nev, nullptr);
     EventGuard guard2{ev2};
     for (auto &e : ev2) PYHEA_HIP(hipEventCreate(&e));
-    for (int i = 0; i < nc; ++i)
-        for (int len = 0; len < 2; ++len) {
-            PYHEA_HIP(copy(o_sp, o_snap, (size_t)g.N));
-            PYHEA_HIP(copy(o_counts, o_snap_counts, E * 4));
-            PYHEA_HIP(copy(o_state, o_snap_state, sizeof(ChainState)));
-            std::vector<hipEvent_t> &v = len == 0 ? ev : ev2;
-            PYHEA_HIP(hipEventRecord(v[2 * i], stream));
-            PYHEA_HIP(run(i, len == 0 ? kProbeBase : kProbeBase + kProbeSteps));
-            PYHEA_HIP(hipEventRecord(v[2 * i + 1], stream));
-        }
+    // repetitions outermost, so that a slow spell of the device touches every candidate alike
+    for (int r = 0; r < kProbeReps; ++r)
+        for (int i = 0; i < nc; ++i)
+            for (int len = 0; len < 2; ++len) {
+                PYHEA_HIP(copy(o_sp, o_snap, (size_t)g.N));
+                PYHEA_HIP(copy(o_counts, o_snap_counts, E * 4));
+                PYHEA_HIP(copy(o_state, o_snap_state, sizeof(ChainState)));
+                std::vector<hipEvent_t> &v = len == 0 ? ev : ev2;
+                const int x = 2 * (r * nc + i);
+                PYHEA_HIP(hipEventRecord(v[x], stream));
+                PYHEA_HIP(run(i, len == 0 ? kProbeBase : kProbeBase + kProbeSteps));
+                PYHEA_HIP(hipEventRecord(v[x + 1], stream));
+            }
     ChainState st;
     PYHEA_HIP(hipMemcpyAsync(&st, base + o_state, sizeof(st), hipMemcpyDeviceToHost, stream));
     PYHEA_HIP(hipStreamSynchronize(stream));
     if (st.status != 0) return PYHEA_OK;   // invalid chain: the real run reports it
-    int bi = 0;
-    double bus = 0.0;
+    std::vector<double> cost(nc);
     for (int i = 0; i < nc; ++i) {
-        float ms0 = 0.0f, ms1 = 0.0f;
-        PYHEA_HIP(hipEventElapsedTime(&ms0, ev[2 * i], ev[2 * i + 1]));
-        PYHEA_HIP(hipEventElapsedTime(&ms1, ev2[2 * i], ev2[2 * i + 1]));
-        const double us = 1e3 * ((double)ms1 - (double)ms0) / kProbeSteps;
-        if (i == 0 || us < bus) {
-            bus = us;
-            bi = i;
+        double d[kProbeReps];
+        for (int r = 0; r < kProbeReps; ++r) {
+            const int x = 2 * (r * nc + i);
+            float ms0 = 0.0f, ms1 = 0.0f;
+            PYHEA_HIP(hipEventElapsedTime(&ms0, ev[x], ev[x + 1]));
+            PYHEA_HIP(hipEventElapsedTime(&ms1, ev2[x], ev2[x + 1]));
+            d[r] = 1e3 * ((double)ms1 - (double)ms0) / kProbeSteps;
         }
+        std::sort(d, d + kProbeReps);
+        cost[i] = d[kProbeReps / 2];
     }
+    int bi = im;
+    for (int i = 0; i < nc; ++i)
+        if (cost[i] < cost[bi]) bi = i;
+    if (cost[bi] > (1.0 - kProbeMargin) * cost[im]) bi = im;
     *best = cand[bi];
-    *us_per_step = bus;
+    *us_per_step = cost[bi];
     *ok = true;
     return PYHEA_OK;
 }
@@ -573,7 +600,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
             if (!have) {
                 double us = 0.0;
                 bool ok = false;
-                const pyhea_status ps = probe_launch(jobs[rep], n, lds_budget, stream, &t, &us, &ok);
+                const pyhea_status ps = probe_launch(jobs[rep], n, lds_budget, shape[rep], stream, &t, &us, &ok);
                 if (ps != PYHEA_OK) return ps;
                 if (ok) record_tuned_launch(key, t, us);
                 have = ok;
@@ -681,6 +708,13 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
                          [&](const Launch &a, const Launch &b) { return longest(a) > longest(b); });
     }
     uint32_t n_tiles = 0;
+    uint64_t total_sites = 0;
+    int max_E = 0;
+    for (int c = 0; c < n; ++c) {
+        total_sites += (uint64_t)jobs[c].g.N;
+        max_E = std::max(max_E, jobs[c].g.S * jobs[c].g.M * jobs[c].g.M);
+    }
+    const uint32_t count_tile = count_tile_for(total_sites);
     {
         CountTask *ht = (CountTask *)hy_at(o_tasks);
         uint32_t *t0 = (uint32_t *)hy_at(o_tile0);
@@ -694,7 +728,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
             b.counts = (int32_t *)(base + o_recount) + eoff[c];
             b.bad = (int32_t *)(base + o_bad2) + c;
             t0[c] = n_tiles;
-            n_tiles += count_tiles((uint32_t)jobs[c].g.N);
+            n_tiles += count_tiles((uint32_t)jobs[c].g.N, count_tile);
         }
     }
     PYHEA_HIP(launch_zero_i32((int32_t *)base, (int64_t)(x_end / 4), stream));
@@ -704,7 +738,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
 
     // initial pair counts of every chain's configuration, in one launch, then the
     // ratio tables from them on the device (an invalid chain is marked and skipped)
-    PYHEA_HIP(launch_count_tasks(tasks, tile0, n, n_tiles, stream));
+    PYHEA_HIP(launch_count_tasks(tasks, tile0, n, n_tiles, count_tile, max_E, stream));
     const ChainDesc *ddev = (const ChainDesc *)(base + o_descs);
     PYHEA_HIP(launch_chain_ratio(ddev, n, (const int32_t *)(base + o_bad), stream));
     std::vector<char> hx(x_end);
@@ -727,7 +761,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
     // results: states with the final objective, maintained counts, and a fresh
     // recount of every final configuration
     PYHEA_HIP(launch_final_objective(ddev, n, stream));
-    PYHEA_HIP(launch_count_tasks(tasks + n, tile0, n, n_tiles, stream));
+    PYHEA_HIP(launch_count_tasks(tasks + n, tile0, n, n_tiles, count_tile, max_E, stream));
     PYHEA_HIP(hipMemcpyAsync(hx.data(), base, x_end, hipMemcpyDeviceToHost, stream));
     PYHEA_HIP(hipStreamSynchronize(stream));
     const int32_t *cnt = (const int32_t *)(hx.data() + o_counts);

@@ -176,16 +176,23 @@ bool count_jobs(const std::vector<Job *> &js, bool recount, void *task_dev, hipS
     std::vector<char> host(n * sizeof(CountTask) + n * 4);
     CountTask *t = (CountTask *)host.data();
     uint32_t *t0 = (uint32_t *)(host.data() + n * sizeof(CountTask));
+    uint64_t total_sites = 0;
+    int max_E = 0;
+    for (size_t i = 0; i < n; ++i) {
+        total_sites += (uint64_t)js[i]->g.N;
+        max_E = std::max(max_E, js[i]->g.S * js[i]->g.M * js[i]->g.M);
+    }
+    const uint32_t tile = count_tile_for(total_sites);
     uint32_t tiles = 0;
     for (size_t i = 0; i < n; ++i) {
         t[i] = count_task(js[i], recount);
         t0[i] = tiles;
-        tiles += count_tiles((uint32_t)js[i]->g.N);
+        tiles += count_tiles((uint32_t)js[i]->g.N, tile);
     }
     bool ok = hipMemcpyAsync(task_dev, host.data(), host.size(), hipMemcpyHostToDevice, s) == hipSuccess;
     ok = ok && launch_count_tasks((const CountTask *)task_dev,
-                                  (const uint32_t *)((char *)task_dev + n * sizeof(CountTask)), (int)n, tiles,
-                                  s) == hipSuccess;
+                                  (const uint32_t *)((char *)task_dev + n * sizeof(CountTask)), (int)n, tiles, tile,
+                                  max_E, s) == hipSuccess;
     return ok;
 }
 

@@ -104,11 +104,14 @@ __global__ void __launch_bounds__(256) count_gather_kernel(EvalDesc ed, int64_t 
 }
 
 // The same gather count for many configurations of different geometries: the
-// grid is the concatenation of every configuration's site tiles.
+// grid is the concatenation of every configuration's site tiles.  The LDS
+// histogram has kHistCopies interleaved copies (bin e, copy c at e * kHistCopies
+// + c; lane l adds into copy l mod kHistCopies), so lanes of a wavefront that
+// hit the same bin hit different words.
+constexpr int kHistCopies = 16;
 __global__ void __launch_bounds__(256) count_tasks_kernel(const CountTask *__restrict__ tasks,
-                                                          const uint32_t *__restrict__ tile0, int n) {
-    __shared__ int32_t hist[kMaxShells * kMaxSpecies * kMaxSpecies];
-    __shared__ int32_t bad_sh;
+                                                          const uint32_t *__restrict__ tile0, int n, uint32_t tile) {
+    extern __shared__ int32_t hist[];   // [E][kHistCopies], then the invalid-id flag
     // owning configuration: the last c with tile0[c] <= blockIdx.x
     int lo = 0, hi = n - 1;
     while (lo < hi) {
@@ -121,16 +124,17 @@ __global__ void __launch_bounds__(256) count_tasks_kernel(const CountTask *__res
     const CountTask &t = tasks[lo];
     const EvalDesc &ed = t.ed;
     const int M = ed.M, E = ed.S * ed.M * ed.M;
-    for (int e = threadIdx.x; e < E; e += blockDim.x) hist[e] = 0;
-    if (threadIdx.x == 0) bad_sh = 0;
+    int32_t *bad_sh = hist + E * kHistCopies;
+    for (int e = threadIdx.x; e <= E * kHistCopies; e += blockDim.x) hist[e] = 0;
     __syncthreads();
     const int8_t *sp = t.species;
-    const uint32_t p0 = (blockIdx.x - tile0[lo]) * (uint32_t)kCountTile;
-    const uint32_t p1 = min(p0 + (uint32_t)kCountTile, ed.N);
+    const int copy = threadIdx.x % kHistCopies;
+    const uint32_t p0 = (blockIdx.x - tile0[lo]) * tile;
+    const uint32_t p1 = min(p0 + tile, ed.N);
     for (uint32_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         const int s = sp[p];
         if (s < 0 || s >= M) {
-            bad_sh = 1;
+            *bad_sh = 1;
             continue;
         }
         const SiteCoord c = site_coord(p, ed.lgA, ed.Lx, ed.Ly, ed.inv_Lx, ed.inv_Ly);
@@ -141,16 +145,18 @@ __global__ void __launch_bounds__(256) count_tasks_kernel(const CountTask *__res
             const int z = wrap1(c.cz + o[2], ed.Lz);
             const int s2 = sp[((z * ed.Ly + y) * ed.Lx + x) * ed.A + o[3]];
             if (s2 < 0 || s2 >= M) continue;
-            atomicAdd(&hist[(o[4] * M + s) * M + s2], 1);
+            atomicAdd(&hist[((o[4] * M + s) * M + s2) * kHistCopies + copy], 1);
         }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < E; e += blockDim.x) {
         const int kk = e / (M * M), i = (e / M) % M, j = e % M;
-        const int v = hist[e] + hist[(kk * M + j) * M + i];
+        const int eT = (kk * M + j) * M + i;
+        int v = 0;
+        for (int q = 0; q < kHistCopies; ++q) v += hist[e * kHistCopies + q] + hist[eT * kHistCopies + q];
         if (v) atomicAdd(&t.counts[e], v);
     }
-    if (threadIdx.x == 0 && bad_sh) atomicOr(t.bad, 1);
+    if (threadIdx.x == 0 && *bad_sh) atomicOr(t.bad, 1);
 }
 
 __global__ void upload_kernel(SmallTable t, int n, double *__restrict__ dst) {
@@ -369,10 +375,12 @@ hipError_t launch_upload(const SmallTable &t, int n, double *dst, hipStream_t st
     return hipGetLastError();
 }
 
-hipError_t launch_count_tasks(const CountTask *tasks, const uint32_t *tile0, int n, uint32_t n_tiles,
-                              hipStream_t stream) {
+hipError_t launch_count_tasks(const CountTask *tasks, const uint32_t *tile0, int n, uint32_t n_tiles, uint32_t tile,
+                              int max_E, hipStream_t stream) {
     if (n <= 0 || n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(count_tasks_kernel, dim3(n_tiles), dim3(256), 0, stream, tasks, tile0, n);
+    if (tile == 0 || max_E <= 0 || max_E > kMaxShells * kMaxSpecies * kMaxSpecies) return hipErrorInvalidValue;
+    const size_t lds = ((size_t)max_E * kHistCopies + 1) * sizeof(int32_t);
+    hipLaunchKernelGGL(count_tasks_kernel, dim3(n_tiles), dim3(256), lds, stream, tasks, tile0, n, tile);
     return hipGetLastError();
 }
 
