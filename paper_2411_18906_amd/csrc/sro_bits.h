@@ -8,7 +8,7 @@
 namespace pyhea {
 
 struct BitDesc {
-    int32_t Lx, Ly, Lz;
+    int32_t Lx, Ly, Lz;  // four-site cells per axis (Lz: the layers of the periodic layout)
     int32_t RS;        // flat row stride in bits (Lx + 2)
     int32_t LW;        // words per plane (flat (Ly + 2) * RS bits)
     int32_t PADW;      // zero words before and after each plane
@@ -20,11 +20,14 @@ struct BitDesc {
     int32_t nchunks;   // workgroups per configuration
     int32_t threads;   // workgroup size
     int32_t partial_stride;
-    uint32_t N;          // sites of the configuration the kernel counts
-    uint32_t cfg_stride; // bytes per configuration in the batch
-    int32_t dbl;         // BCC with an odd number of cells along x, counted as
-                         // the configuration repeated twice along x (N = 2 x
-                         // the original's sites; counts are halved on output)
+    uint32_t N;
+    // BCC with an odd number of cells along x: a four-site cell is BCC cell
+    // (x, y, 2z) and (x, y, 2z + 1) along z (zpair = 1; Lzs = the BCC cells
+    // along z).  With Lzs odd the layout holds the configuration twice along z
+    // (Lz = Lzs layers) and only BCC layers 0 .. Lzs - 1 are centres: layers
+    // 0 .. Lzc - 2 whole, and layer Lzc - 1 for its first BCC layer only
+    // (half_last = 1).  Otherwise Lzc = Lz.
+    int32_t zpair, Lzs, Lzc, half_last;
     int32_t nh;
     int32_t hstart[kMaxShells + 1];
     int32_t zk[kMaxShells];
@@ -47,7 +50,6 @@ struct StreamDesc {
     int32_t threads;
     int32_t maxd;           // load blocks per lane the kernel holds offsets for
     int32_t grid;           // persistent workgroups
-    int32_t dbl;            // always 0 (the doubled BCC layout is the bit-sliced kernel's)
     uint32_t N;
     int32_t zk[kMaxShells];
     int32_t hs[4][2][kMaxShells + 1];   // per basis and layer step dz: start of shell k's half offsets
@@ -64,8 +66,7 @@ hipError_t launch_count_stream(const Geometry &g, const StreamDesc &sd, int64_t 
 
 // Fills bd; false if the bit-sliced kernel does not cover this geometry (it
 // covers FCC and BCC for shells whose neighbours lie at most one cell away;
-// a BCC cell with an odd number of cells along x is counted as itself repeated
-// twice along x, whose pair counts are exactly twice its own).
+// four-site cells pair BCC cells along x, or along z when Lx is odd).
 // K is the number of configurations of the launch: few configurations are
 // split along z over more workgroups.  With split > 1, a configuration whose
 // layers would take more than 1/split of a CU's LDS is cut along z so that

@@ -106,7 +106,7 @@ __device__ __forceinline__ void epilogue(const int32_t *pairs, const Desc &bd, i
     }
     __syncthreads();
     for (int e = tid; e < S * M * M; e += blockDim.x) {
-        cnt[e] = bd.dbl ? lc[e] / 2 : lc[e];   // a doubled layout counts every pair twice
+        cnt[e] = lc[e];
         if (S_F) {
             const int k = e / (M * M), i = (e / M) % M, j = e % M;
             const double R = (double)bd.N / (double)(n[i] * n[j] * (int64_t)bd.zk[k]);
@@ -279,7 +279,7 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
     if (kc >= K) return;
     const int chunk = blockIdx.x;
     const int z0 = chunk * bd.ZC;
-    const int nz = min(bd.ZC, bd.Lz - z0);   // centre layers of this workgroup
+    const int nz = min(bd.ZC, bd.Lzc - z0);  // centre layers of this workgroup
     const int nl = nz + 1;                   // plus the next layer (dz in {0, 1})
     const int PW = bd.PW;
     const int RS = bd.RS;
@@ -316,7 +316,7 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
     __syncthreads();
 
     // ---- 1. conversion: one padded row (layer ll, row fy) per item ------------------
-    const uint8_t *cfg = reinterpret_cast<const uint8_t *>(species) + kc * (int64_t)bd.cfg_stride;
+    const uint8_t *cfg = reinterpret_cast<const uint8_t *>(species) + kc * (int64_t)bd.N;
     uint32_t badacc = 0;
     const uint32_t kBad = (0x80u - M) * 0x01010101u;   // byte + kBad has bit 7 set iff byte >= M (bytes < 0x80)
     const int rows = bd.Ly + 2;
@@ -331,6 +331,15 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
         int cz = z0 + ll;
         if (cz >= bd.Lz) cz -= bd.Lz;
         const uint32_t rowoff = (uint32_t)((cz * bd.Ly + cy) * bd.Lx) * 4u;
+        // z-paired BCC: the row's two BCC rows (layers 2 cz and 2 cz + 1 mod Lzs), 2 Lx bytes each
+        uint32_t rowlo = 0, rowhi = 0;
+        if (bd.zpair) {
+            int zl = 2 * cz;
+            zl = zl >= bd.Lzs ? zl - bd.Lzs : zl;
+            const int zh = zl + 1 >= bd.Lzs ? zl + 1 - bd.Lzs : zl + 1;
+            rowlo = (uint32_t)((zl * bd.Ly + cy) * bd.Lx) * 2u;
+            rowhi = (uint32_t)((zh * bd.Ly + cy) * bd.Lx) * 2u;
+        }
 #pragma unroll 1
         for (int cxc = 0; cxc < bd.nchx; ++cxc) {
             constexpr int ND = Digits<M>::ND;
@@ -401,13 +410,9 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
                     for (int m = 0; m < 8; ++m) {
                         int c = 32 * cxc + 8 * g + m - 1;
                         c = c < 0 ? bd.Lx - 1 : (c >= bd.Lx ? 0 : c);
-                        if (bd.dbl) {   // uniform: four-site cell c = BCC cells 2c, 2c + 1 (mod Lx) of the row
-                            const uint32_t row2 = rowoff >> 1;   // the BCC row: 2 Lx bytes
-                            int lo = 2 * c, hi = 2 * c + 1;
-                            lo = lo >= bd.Lx ? lo - bd.Lx : lo;
-                            hi = hi >= bd.Lx ? hi - bd.Lx : hi;
-                            const uint32_t a = *reinterpret_cast<const uint16_t *>(cfg + (row2 + 2u * (uint32_t)lo));
-                            const uint32_t b = *reinterpret_cast<const uint16_t *>(cfg + (row2 + 2u * (uint32_t)hi));
+                        if (bd.zpair) {   // uniform: sublattices 0, 1 from the lower BCC row, 2, 3 from the upper
+                            const uint32_t a = *reinterpret_cast<const uint16_t *>(cfg + (rowlo + 2u * (uint32_t)c));
+                            const uint32_t b = *reinterpret_cast<const uint16_t *>(cfg + (rowhi + 2u * (uint32_t)c));
                             d[gg][m] = a | (b << 16);
                         } else {
                             d[gg][m] = *reinterpret_cast<const uint32_t *>(cfg + (rowoff + 4u * (uint32_t)c));
@@ -507,6 +512,8 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
             const int rem = it - bu * nbw64;
             if (rem >= nbw) continue;   // padding
             const int ll = qdiv(rem, inv_ncw);
+            // z-paired BCC with an odd Lzs: the last centre layer's upper BCC layer repeats layer 0
+            if (bu >= 2 && bd.half_last && z0 + ll == bd.Lzc - 1) continue;
             const int w = bd.cw0 + rem - ll * bd.NCW;
             const uint32_t *lbase = lds + (ll * 4 * PW + bd.PADW + w) * P;
             uint32_t Pv[P], Un[NP];
@@ -537,6 +544,7 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
             const int w = bd.cw0 + it - lb * bd.NCW;
             const int b = lb & 3;
             const int ll = lb >> 2;
+            if (b >= 2 && bd.half_last && z0 + ll == bd.Lzc - 1) continue;   // as above
             const uint32_t *lbase = lds + (ll * 4 * PW + bd.PADW + w) * P;
             uint32_t Pv[P], Un[NP];
             centre_word<M>(lbase + b * PW * P, cmask[w], slots, Pv, Un);
@@ -628,8 +636,6 @@ __global__ void finalize_bits_kernel(BitDesc bd, int64_t K, const int32_t *__res
     n[M - 1] = rest;
     bad[kc] = pa[S * NP + P] ? 1 : 0;
     for (int k = 0; k < S; ++k) expand_shell<M>(pa + k * NP, bd.zk[k], n, c + k * M * M);
-    if (bd.dbl)   // a doubled layout counts every pair twice
-        for (int e = 0; e < S * M * M; ++e) c[e] /= 2;
 }
 
 // slot sums -> counts and Eq. 2-3 (one 64-thread block per configuration)
@@ -1037,7 +1043,7 @@ hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_
     for (int64_t k0 = 0; k0 < K; k0 += 65535) {
         const int64_t kn = std::min<int64_t>(65535, K - k0);
         hipLaunchKernelGGL(fn, dim3(bd.nchunks, (unsigned)kn), dim3(bd.threads), lds, stream, bd, kn,
-                           species + k0 * (int64_t)bd.cfg_stride, partial + k0 * bd.nchunks * bd.partial_stride,
+                           species + k0 * (int64_t)bd.N, partial + k0 * bd.nchunks * bd.partial_stride,
                            counts + k0 * (int64_t)(S * M * M), bad + k0, tw, S_F ? S_F + 2 * k0 : nullptr);
     }
     if (bd.nchunks > 1 && S_F)
@@ -1081,7 +1087,10 @@ LaunchFn pick(int M, int S) {
 // Cell delta and target sublattice of offset t from sublattice b of a
 // four-site cell (an FCC cell, or two BCC cells along x: BCC site (2X + e,
 // b & 1) of four-site cell X, e = b >> 1).
-static void four_site_target(const Geometry &g, int b, int t, int dc[3], int *bt) {
+// Four-site cells: an FCC cell, or two BCC cells adjacent along `axis` (0 = x,
+// 2 = z); sublattice 2 e + b is BCC basis b of the pair's cell e.  Cell delta
+// dc and sublattice bt of the target of offset t from sublattice b.
+static void four_site_target(const Geometry &g, int axis, int b, int t, int dc[3], int *bt) {
     if (g.lattice == PYHEA_FCC) {
         offset_target(g, b, t, dc, bt);
         return;
@@ -1089,11 +1098,12 @@ static void four_site_target(const Geometry &g, int b, int t, int dc[3], int *bt
     const int e = b >> 1;
     int dcb[3], btb;
     offset_target(g, b & 1, t, dcb, &btb);
-    const int x = e + dcb[0];
+    const int x = e + dcb[axis];
     const int X = x >= 0 ? x / 2 : -((1 - x) / 2);
-    dc[0] = X;
+    dc[0] = dcb[0];
     dc[1] = dcb[1];
     dc[2] = dcb[2];
+    dc[axis] = X;
     *bt = 2 * (x - 2 * X) + btb;
 }
 
@@ -1102,33 +1112,39 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitD
     if (g.halo != 1 || !pick(g.M, g.S)) return false;
     // Cells of four sites: an FCC cell, or two BCC cells along x (site id
     // ((cz Ly + cy) Lx + cx) 2 + b is ((cz Ly + cy) (Lx/2) + cx/2) 4 + 2 (cx % 2) + b,
-    // so an even-Lx BCC configuration is laid out as cells of four sublattices)
-    int Lx4;
-    int dbl = 0;
+    // so an even-Lx BCC configuration is laid out as cells of four sublattices).
+    // With Lx odd the pairs run along z instead: four-site layer z holds BCC
+    // layers 2z and 2z + 1, read as two rows of 2 Lx bytes.  An odd Lz makes the
+    // pairs wrap: the layout then holds the configuration twice along z (Lz
+    // four-site layers = 2 Lz BCC layers, periodic with period Lz, so every
+    // centre sees the neighbours it has in the configuration) and counts only
+    // the first copy's sites as centres.
+    int Lx4, Lz4 = g.L[2], Lzc = g.L[2], zpair = 0, half_last = 0;
     if (g.lattice == PYHEA_FCC) {
         Lx4 = g.L[0];
     } else if (g.lattice == PYHEA_BCC && g.L[0] % 2 == 0) {
         Lx4 = g.L[0] / 2;
     } else if (g.lattice == PYHEA_BCC) {
-        // odd Lx: the configuration repeated twice along x (2 Lx BCC cells = Lx
-        // four-site cells).  Every (site, offset) pair of the repeated cell has
-        // the species pair of its image in the original (the species pattern
-        // has period Lx), so its counts are exactly twice the original's, and
-        // alpha, S and F (Eq. 2-3) are unchanged bit for bit (N, n_i, n_j and
-        // N_ij all double: powers of two scale binary64 exactly).
         Lx4 = g.L[0];
-        dbl = 1;
-        int zmax = 0;
-        for (int k = 0; k < g.S; ++k) zmax = std::max(zmax, g.z[k]);
-        if (2 * g.N * (int64_t)zmax >= ((int64_t)1 << 31)) return false;   // doubled counts stay int32
+        zpair = 1;
+        if (g.L[2] % 2 == 0) {
+            Lz4 = Lzc = g.L[2] / 2;
+        } else {
+            Lz4 = g.L[2];
+            Lzc = (g.L[2] + 1) / 2;
+            half_last = 1;
+        }
     } else {
         return false;
     }
     const int P = g.M - 1;
     bd->Lx = Lx4;
-    bd->dbl = dbl;
     bd->Ly = g.L[1];
-    bd->Lz = g.L[2];
+    bd->Lz = Lz4;
+    bd->zpair = zpair;
+    bd->Lzs = g.L[2];
+    bd->Lzc = Lzc;
+    bd->half_last = half_last;
     bd->RS = Lx4 + 2;
     const int bits = (g.L[1] + 2) * bd->RS;
     bd->LW = (bits + 31) / 32;
@@ -1137,8 +1153,7 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitD
     bd->cw0 = bd->RS / 32;
     bd->NCW = ((g.L[1] + 1) * bd->RS - 1) / 32 - bd->cw0 + 1;
     bd->nchx = (bd->RS + 31) / 32;
-    bd->N = (uint32_t)(dbl ? 2 * g.N : g.N);
-    bd->cfg_stride = (uint32_t)g.N;
+    bd->N = (uint32_t)g.N;
     const int np = P * (P + 1) / 2;
     bd->partial_stride = ((g.S * np + P + 1) + 3) & ~3;
     for (int k = 0; k < kMaxShells; ++k) bd->zk[k] = k < g.S ? g.z[k] : 0;
@@ -1148,17 +1163,17 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitD
     const int per_layer = 4 * P * bd->PW * 4;
     // split > 1: a configuration whose layers would take more than 1/split of a
     // CU's LDS is cut along z so that `split` workgroups share each CU
-    const int budget = split > 1 && fixed + (g.L[2] + 1) * per_layer > lds_budget / split ? lds_budget / split
-                                                                                          : lds_budget;
+    const int budget = split > 1 && fixed + (Lzc + 1) * per_layer > lds_budget / split ? lds_budget / split
+                                                                                        : lds_budget;
     int zc = (budget - fixed) / per_layer - 1;
     if (zc < 1) return false;
-    zc = std::min(zc, g.L[2]);
-    zc = (g.L[2] + (g.L[2] + zc - 1) / zc - 1) / ((g.L[2] + zc - 1) / zc);
+    zc = std::min(zc, Lzc);
+    zc = (Lzc + (Lzc + zc - 1) / zc - 1) / ((Lzc + zc - 1) / zc);
     // few configurations: spread each over up to 512 / K workgroups along z
     const int64_t want = std::max<int64_t>(1, 512 / std::max<int64_t>(K, 1));
-    if (want > 1) zc = std::min<int64_t>(zc, std::max<int64_t>(2, (g.L[2] + want - 1) / want));
+    if (want > 1) zc = std::min<int64_t>(zc, std::max<int64_t>(2, (Lzc + want - 1) / want));
     bd->ZC = zc;
-    bd->nchunks = (g.L[2] + zc - 1) / zc;
+    bd->nchunks = (Lzc + zc - 1) / zc;
     // a workgroup that needs more than half the LDS runs alone on its CU: give it
     // 16 wavefronts so the CU still has latency to hide behind
     bd->threads = fixed + (zc + 1) * per_layer > lds_budget / 2 ? 1024 : 512;
@@ -1172,7 +1187,7 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitD
             if (!keep) continue;
             for (int b = 0; b < 4; ++b) {
                 int dc[3], bt;
-                four_site_target(g, b, t, dc, &bt);
+                four_site_target(g, zpair ? 2 : 0, b, t, dc, &bt);
                 // the layout covers cell deltas of -1..1 along x and y, 0..1 along z
                 if (dc[0] < -1 || dc[0] > 1 || dc[1] < -1 || dc[1] > 1 || dc[2] < 0 || dc[2] > 1) return false;
                 // plane word of the neighbour: layer +dz, sublattice bt, bit shift s
@@ -1196,7 +1211,7 @@ hipError_t launch_count_bits(const Geometry &g, const BitDesc &bd, int64_t K, co
     LaunchFn f = pick(g.M, g.S);
     if (!f) return hipErrorInvalidValue;
     BitDesc b = bd;
-    b.vec4 = !bd.dbl && bd.Lx % 4 == 0 && (reinterpret_cast<uintptr_t>(species) & 15) == 0 ? 1 : 0;
+    b.vec4 = !bd.zpair && bd.Lx % 4 == 0 && (reinterpret_cast<uintptr_t>(species) & 15) == 0 ? 1 : 0;
     return f(b, K, species, partial, counts, bad, tw, S_F, stream);
 }
 
@@ -1291,7 +1306,7 @@ bool fill_stream_desc(const Geometry &g, int lds_budget, int n_cus, int64_t K, i
                     const bool keep = dzh > 0 || (dzh == 0 && (dy > 0 || (dy == 0 && dx > 0)));
                     if (!keep) continue;
                     int dc[3], bt;
-                    four_site_target(g, b, t, dc, &bt);
+                    four_site_target(g, 0, b, t, dc, &bt);
                     if (dc[0] < -1 || dc[0] > 1 || dc[1] < -1 || dc[1] > 1 || dc[2] < 0 || dc[2] > 1) return false;
                     if (dc[2] != dz) continue;
                     const int sh = dc[1] * sd->RS + dc[0];

@@ -91,9 +91,12 @@ BATCH_SHAPES = [
     # BCC with even Lx runs on the four-site-cell layout; shell 4 uses gathers
     (orc.BCC, (8, 8, 8), 5, 3, 20), (orc.BCC, (2, 3, 3), 3, 3, 7), (orc.BCC, (10, 4, 6), 6, 2, 9),
     (orc.BCC, (64, 32, 32), 4, 2, 3), (orc.BCC, (7, 4, 4), 3, 2, 5), (orc.BCC, (4, 4, 4), 4, 4, 4),
-    # BCC with odd Lx: counted as the configuration repeated twice along x
+    # BCC with odd Lx: cells paired along z (even Lz), or along z over the
+    # configuration held twice along z with the first copy's sites as centres (odd Lz)
     (orc.BCC, (31, 31, 31), 5, 3, 3), (orc.BCC, (3, 5, 4), 6, 2, 12), (orc.BCC, (1, 3, 3), 4, 1, 6),
-    (orc.BCC, (9, 2, 7), 3, 3, 9), (orc.BCC, (33, 6, 5), 8, 2, 4),
+    (orc.BCC, (9, 2, 7), 3, 3, 9), (orc.BCC, (33, 6, 5), 8, 2, 4), (orc.BCC, (5, 3, 2), 4, 3, 7),
+    (orc.BCC, (7, 4, 6), 5, 2, 5), (orc.BCC, (3, 3, 1), 3, 1, 8), (orc.BCC, (31, 32, 32), 4, 2, 3),
+    (orc.BCC, (5, 6, 9), 7, 3, 3),
     # counting order: a two-layer workgroup with 60-64 centre words per basis walks
     # them basis-major (padded to one wavefront), a one-layer workgroup layer-major;
     # the first three launches hold one of each
