@@ -108,6 +108,8 @@ typedef struct {
                             2 HBM) * 10000 + steps per pass * 100 + commit chunk */
     int32_t shape_measured; /* 1 if that shape was chosen by measurement (this
                             call or an earlier one), 0 by the cost model      */
+    int32_t graph;       /* 1 if the call's device work ran as a replay of the
+                            graph recorded for its structure (pyhea_tune_graphs) */
 } pyhea_mc_stats;
 
 /* Global search parameters (Sec. 4.1, Algorithm 1; the parameter study of
@@ -397,6 +399,22 @@ pyhea_status pyhea_tune_force(int32_t variant);
  * model, which was fitted to batches.  on = 0 uses the cost model alone.
  * The shape used is reported in pyhea_mc_stats.  Shapes never change results. */
 pyhea_status pyhea_tune_measure(int32_t on);
+
+/* Recorded device work of chain calls (pyhea_mc_run, pyhea_mc_batch; on by
+ * default).  A call's device work -- the zeroed result block, the initial
+ * counts, the ratio tables, the chain launches on up to four streams, the
+ * final objective and the recount -- depends only on its structure: the
+ * chains' geometries and launch shapes, which fix the device buffer layout.
+ * The second call of a structure records that work as a hipGraph on a buffer
+ * the library keeps, and it and later calls of the structure upload their
+ * descriptors (seeds, trial counts, species and log pointers, targets) and
+ * replay the graph: one launch instead of about ten, and no stream forks.  At
+ * most 32 structures are recorded per process, each keeping its device
+ * buffer (descriptors, counts, ratio tables, padded copies of HBM-store
+ * chains) until the process ends; calls of other structures run eagerly.
+ * Calls of one structure from several threads take turns.  Results never
+ * depend on this.  on = 0 runs every call eagerly. */
+pyhea_status pyhea_tune_graphs(int32_t on);
 
 /* Full-evaluation kernel: -1 = automatic (bit-sliced where it covers the
  * geometry, else gather), 0 = gather, 1 = bit-sliced where possible (a

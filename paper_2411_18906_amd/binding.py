@@ -29,7 +29,7 @@ EXPORTS = [
     "pyhea_serve_close", "pyhea_philox4x32_10", "pyhea_tune_force",
     "pyhea_tune_force_eval", "pyhea_tune_force_lookahead", "pyhea_global_search",
     "pyhea_random_configs", "pyhea_trial_eval_full", "pyhea_sro_eval_batch_noalloc",
-    "pyhea_tune_force_stream", "pyhea_map_sites", "pyhea_tune_measure",
+    "pyhea_tune_force_stream", "pyhea_map_sites", "pyhea_tune_measure", "pyhea_tune_graphs",
 ]
 
 
@@ -74,7 +74,7 @@ class McStats(ctypes.Structure):
                 ("commits", ctypes.c_int64), ("steps", ctypes.c_int64),
                 ("stop_reason", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("S", ctypes.c_double), ("F", ctypes.c_double), ("log_len", ctypes.c_int64),
-                ("shape", ctypes.c_int32), ("shape_measured", ctypes.c_int32)]
+                ("shape", ctypes.c_int32), ("shape_measured", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -112,6 +112,7 @@ def lib():
             "pyhea_tune_force_stream": ([i32, i32], i32),
             "pyhea_map_sites": ([P, P, ctypes.c_double, i64, P, P, P, P, P], i32),
             "pyhea_tune_measure": ([i32], i32),
+            "pyhea_tune_graphs": ([i32], i32),
             "pyhea_tune_force_lookahead": ([i32], i32),
             "pyhea_global_search": ([P, P, P, P, P, P, P, P], i32),
             "pyhea_random_configs": ([i64, i32, P, u64, ctypes.c_uint32, ctypes.c_uint32, i32, P, P], i32),
@@ -444,6 +445,11 @@ def pyhea_tune_force_eval(kernel: int):
 
 def pyhea_tune_measure(on: bool):
     _check(lib().pyhea_tune_measure(1 if on else 0))
+
+
+def pyhea_tune_graphs(on: bool):
+    """Replay recorded graphs for repeated chain calls of one structure (default on)."""
+    _check(lib().pyhea_tune_graphs(1 if on else 0))
 
 
 def pyhea_tune_force_stream(layers_per_group: int, threads: int):

@@ -635,6 +635,15 @@ pyhea_status pyhea_tune_measure(int32_t on) {
     return guard(PYHEA_OK);
 }
 
+pyhea_status pyhea_tune_graphs(int32_t on) {
+    if (on != 0 && on != 1) {
+        set_error("on must be 0 or 1");
+        return PYHEA_EINVAL;
+    }
+    set_graphs_enabled(on != 0);
+    return guard(PYHEA_OK);
+}
+
 pyhea_status pyhea_tune_force_lookahead(int32_t steps) {
     if (steps < 0 || steps > kMaxLookahead) {
         set_error("steps per pass must be 0 (automatic) or 1..8");

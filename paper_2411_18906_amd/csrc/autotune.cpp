@@ -23,6 +23,7 @@ int g_forced_eval = -1;
 int g_stream_G = 0, g_stream_threads = 0;
 int g_forced_lookahead = 0;
 bool g_measure = true;
+bool g_graphs = true;
 
 // measured shapes by key string; loaded from the cache file on first use
 std::mutex g_tune_mu;
@@ -149,6 +150,16 @@ bool measure_enabled() {
 void set_measure_enabled(bool on) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_measure = on;
+}
+
+bool graphs_enabled() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_graphs;
+}
+
+void set_graphs_enabled(bool on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_graphs = on;
 }
 
 int wave_budget(int n_chains) {

@@ -60,6 +60,10 @@ void record_tuned_launch(const TuneKey &k, const LaunchShape &s, double us_per_s
 // Whether automatic shapes are measured (pyhea_tune_measure; on by default).
 bool measure_enabled();
 void set_measure_enabled(bool on);
+// Whether repeated chain calls of one structure replay a recorded graph
+// (pyhea_tune_graphs; on by default).
+bool graphs_enabled();
+void set_graphs_enabled(bool on);
 // Encoded launch shape reported in the chain statistics:
 // store * 10000 + steps per pass * 100 + commit chunk.
 inline int32_t shape_code(const LaunchShape &s) { return s.store * 10000 + s.K * 100 + s.CH; }

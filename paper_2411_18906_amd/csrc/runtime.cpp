@@ -3,6 +3,7 @@
 #include "runtime.h"
 
 #include <algorithm>
+#include <list>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -269,24 +270,28 @@ struct DeviceBuffer {
 // Auxiliary streams (default priority, non-blocking) on which launches of
 // different shapes run beside the caller's stream; created once per device,
 // kept until exit.  Three, so that with the caller's stream they map onto the
-// four hardware queues a process gets by default.
+// four hardware queues a process gets by default.  Set 1 is a separate main
+// stream and three auxiliary streams used only to record graphs, so that a
+// recording never meets work that other calls put on set 0.
 constexpr int kAuxStreams = 3;
 
-bool aux_streams(hipStream_t *out) {
+bool stream_set(int set, hipStream_t *out, int count) {
     static std::mutex mu;
-    static hipStream_t pool[64][kAuxStreams];
-    static bool made[64] = {false};
+    static hipStream_t pool[2][64][kAuxStreams + 1];
+    static bool made[2][64] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
     std::lock_guard<std::mutex> lock(mu);
-    if (!made[dev]) {
-        for (int i = 0; i < kAuxStreams; ++i)
-            if (hipStreamCreateWithFlags(&pool[dev][i], hipStreamNonBlocking) != hipSuccess) return false;
-        made[dev] = true;
+    if (!made[set][dev]) {
+        for (int i = 0; i <= kAuxStreams; ++i)
+            if (hipStreamCreateWithFlags(&pool[set][dev][i], hipStreamNonBlocking) != hipSuccess) return false;
+        made[set][dev] = true;
     }
-    for (int i = 0; i < kAuxStreams; ++i) out[i] = pool[dev][i];
+    for (int i = 0; i < count; ++i) out[i] = pool[set][dev][i];
     return true;
 }
+
+bool aux_streams(hipStream_t *out) { return stream_set(0, out, kAuxStreams); }
 
 // Events that fork work from `main` onto aux streams and join it back.
 struct Fork {
@@ -300,11 +305,14 @@ struct Fork {
         for (int i = 0; i < used; ++i) (void)hipStreamSynchronize(aux[i]);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
     }
-    // launch i goes to the caller's stream (i % (used + 1) == 0) or aux stream
-    hipError_t begin(hipStream_t m, int n_launches) {
+    // launch i goes to the caller's stream (i % (used + 1) == 0) or aux stream;
+    // aux_set: the auxiliary streams to use (nullptr: the shared ones)
+    hipError_t begin(hipStream_t m, int n_launches, const hipStream_t *aux_set = nullptr) {
         main = m;
         used = std::min(n_launches - 1, kAuxStreams);
-        if (used <= 0 || !aux_streams(aux)) {
+        if (used > 0 && aux_set) {
+            for (int i = 0; i < kAuxStreams; ++i) aux[i] = aux_set[i];
+        } else if (used <= 0 || !aux_streams(aux)) {
             used = 0;  // everything stays on the caller's stream
             return hipSuccess;
         }
@@ -526,6 +534,81 @@ pyhea_status probe_launch(const ChainJob &j, int n_chains, int lds_budget, const
 
 }  // namespace
 
+namespace {
+
+// Recorded device work of chain calls: a persistent arena and the graph that
+// runs a call's launches on it (run_chains).  A structure is recorded the
+// second time it is seen, so one-off calls never pay for recording.  Plans are
+// never destroyed: at most kMaxPlans are made per process, and calls of other
+// structures then run eagerly.  (A test that dropped the least recently used
+// plan -- destroying its executable graph and freeing its arena -- ended in a
+// host segmentation fault whose cause was not found, so nothing is dropped.)
+// A call holds its plan's mutex from the upload to the read-back, so calls of
+// one structure from several threads take turns on its arena.
+struct ChainPlan {
+    std::vector<int64_t> key;
+    void *arena = nullptr;
+    hipGraph_t graph = nullptr;   // kept beside its executable form
+    hipGraphExec_t exec = nullptr;
+    bool failed = false;          // recording was refused: calls run eagerly
+    std::mutex mu;
+};
+constexpr size_t kMaxPlans = 32;
+constexpr size_t kSeenKeys = 16;
+std::mutex g_plan_mu;
+auto *g_plans = new std::list<ChainPlan *>();          // most recently used first; never freed
+auto *g_seen = new std::list<std::vector<int64_t>>();  // structures seen once
+
+// The plan for `key` (arena of `bytes`), or none: on the first sighting, and
+// once kMaxPlans plans exist.
+hipError_t chain_plan(const std::vector<int64_t> &key, size_t bytes, ChainPlan **out) {
+    *out = nullptr;
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    for (auto it = g_plans->begin(); it != g_plans->end(); ++it)
+        if ((*it)->key == key) {
+            *out = *it;
+            g_plans->splice(g_plans->begin(), *g_plans, it);
+            return hipSuccess;
+        }
+    if (g_plans->size() >= kMaxPlans) return hipSuccess;
+    auto seen = std::find(g_seen->begin(), g_seen->end(), key);
+    if (seen == g_seen->end()) {
+        g_seen->push_front(key);
+        if (g_seen->size() > kSeenKeys) g_seen->pop_back();
+        return hipSuccess;
+    }
+    g_seen->erase(seen);
+    void *arena = nullptr;
+    const hipError_t e = hipMalloc(&arena, bytes);
+    if (e != hipSuccess) return e;
+    ChainPlan *p = new ChainPlan();
+    p->key = key;
+    p->arena = arena;
+    g_plans->push_front(p);
+    *out = p;
+    return hipSuccess;
+}
+
+// Records work(stream, aux streams) into p->graph and p->exec on the recording
+// streams.  On failure the plan stays without a graph and its calls run eagerly.
+template <class Work>
+hipError_t record_plan(ChainPlan *p, Work &work) {
+    hipStream_t st[kAuxStreams + 1];
+    if (!stream_set(1, st, kAuxStreams + 1)) return hipErrorInvalidValue;
+    hipError_t e = hipStreamBeginCapture(st[0], hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return e;
+    const hipError_t ew = work(st[0], st + 1);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(st[0], &graph);
+    if (ew != hipSuccess || e != hipSuccess) return ew != hipSuccess ? ew : e;
+    p->graph = graph;
+    e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) p->exec = nullptr;
+    return e;
+}
+
+}  // namespace
+
 pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
                         std::vector<std::vector<int64_t>> *final_counts, hipStream_t stream,
                         int variant) {
@@ -623,89 +706,45 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
             off += (size_t)jobs[c].g.Npad;
         }
     }
-    DeviceBuffer arena;
-    arena.stream = stream;
-    PYHEA_HIP(pool_alloc(&arena.ptr, off, stream));
-    char *base = (char *)arena.ptr;
-
-    // block Y on the host: targets, chain descriptors (ordered by launch group), count tasks
-    std::vector<char> hy(y_end - y_begin, 0);
-    auto hy_at = [&](size_t o) { return hy.data() + (o - y_begin); };
-    for (int c = 0; c < n; ++c)
-        std::memcpy(hy_at(o_target) + eoff[c] * 8, jobs[c].target.data(), jobs[c].target.size() * 8);
-    std::vector<ChainDesc> descs(n);
-    std::map<std::tuple<int, int, int, int, int, int, int, int>, std::vector<int>> groups;
-    for (int c = 0; c < n; ++c) {
-        const ChainJob &j = jobs[c];
-        ChainDesc &d = descs[c];
-        std::memset(&d, 0, sizeof(d));
-        fill_chain_geometry(j.g, &d);
-        d.seed = j.params.seed;
-        d.chain_id = j.params.chain_id;
-        d.B = j.params.cand_per_step;
-        d.n_trials = j.params.n_trials;
-        d.mode = j.params.commit_mode;
-        d.depth_limit = j.params.depth_limit;
-        d.tau = j.params.accept_tol;
-        for (int k = 0; k < kMaxShells; ++k) d.w[k] = k < j.g.S ? j.weight[k] : 0.0;
-        d.species = j.species_dev;
-        d.pad_global = shape[c].store == kStoreGlobal ? (int8_t *)(base + o_pad[c]) : nullptr;
-        d.R = (const double *)(base + o_R) + eoff[c];
-        d.target = (const double *)(base + o_target) + eoff[c];
-        d.counts = (int32_t *)(base + o_counts) + eoff[c];
-        d.log = j.log_dev;
-        d.log_cap = j.log_dev ? j.log_cap : 0;
-        d.state = (ChainState *)(base + o_state) + c;
-        d.store = shape[c].store;
-        d.lds_bytes = shape[c].lds;
-        d.sym = symmetric_target(j.target.data(), j.g.S, j.g.M);
-        groups[{shape[c].store, j.g.M, j.g.S, d.B, shape[c].W, shape[c].bal, shape[c].K, shape[c].CH}].push_back(c);
-    }
+    // launch groups: chains of one shape share a launch, longest chains first
+    // (trials x offsets gathered per trial) so that its tail is short; then the
+    // launch whose longest chain is longest (per-trial cost taken as offsets
+    // gathered plus count entries evaluated) goes first, so it starts first
     struct Launch {
         int first, count, store, M, S, B, W, bal, K, CH, lds;
     };
     std::vector<Launch> launches;
     std::vector<int> pos(n);   // descriptor position of each chain
     {
-        ChainDesc *hd = (ChainDesc *)hy_at(o_descs);
+        std::map<std::tuple<int, int, int, int, int, int, int, int>, std::vector<int>> groups;
+        for (int c = 0; c < n; ++c)
+            groups[{shape[c].store, jobs[c].g.M, jobs[c].g.S, jobs[c].params.cand_per_step, shape[c].W, shape[c].bal,
+                    shape[c].K, shape[c].CH}]
+                .push_back(c);
         int at = 0;
+        std::vector<std::pair<int64_t, Launch>> byw;
         for (auto &kv : groups) {
-            // longest chains first (trials x offsets gathered per trial) so the tail
-            // of the launch is short
             std::vector<int> idx = kv.second;
             std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
                 return jobs[a].params.n_trials * jobs[a].g.Z > jobs[b].params.n_trials * jobs[b].g.Z;
             });
-            Launch L{at,
-                     (int)idx.size(),
-                     std::get<0>(kv.first),
-                     std::get<1>(kv.first),
-                     std::get<2>(kv.first),
-                     std::get<3>(kv.first),
-                     std::get<4>(kv.first),
-                     std::get<5>(kv.first),
-                     std::get<6>(kv.first),
-                     std::get<7>(kv.first),
-                     0};
-            for (int c : idx) {
-                L.lds = std::max(L.lds, descs[c].lds_bytes);
-                pos[c] = at;
-                hd[at++] = descs[c];
-            }
-            launches.push_back(L);
-        }
-        // the launch with the longest chain first, so it starts first (per-trial cost
-        // taken as offsets gathered plus count entries evaluated)
-        auto longest = [&](const Launch &L) {
+            Launch L{at, (int)idx.size(), std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                     std::get<3>(kv.first), std::get<4>(kv.first), std::get<5>(kv.first), std::get<6>(kv.first),
+                     std::get<7>(kv.first), 0};
             int64_t w = 0;
-            for (int i = L.first; i < L.first + L.count; ++i) {
-                const ChainDesc &d = hd[i];
-                w = std::max<int64_t>(w, d.n_trials * (int64_t)(d.zstart[d.S] + d.M * d.M));
+            for (int c : idx) {
+                L.lds = std::max(L.lds, shape[c].lds);
+                pos[c] = at++;
+                const Geometry &g = jobs[c].g;
+                w = std::max<int64_t>(w, jobs[c].params.n_trials * (int64_t)(g.zstart[g.S] + g.M * g.M));
             }
-            return w;
-        };
-        std::stable_sort(launches.begin(), launches.end(),
-                         [&](const Launch &a, const Launch &b) { return longest(a) > longest(b); });
+            byw.push_back({w, L});
+        }
+        std::stable_sort(byw.begin(), byw.end(),
+                         [](const std::pair<int64_t, Launch> &x, const std::pair<int64_t, Launch> &y) {
+                             return x.first > y.first;
+                         });
+        for (auto &x : byw) launches.push_back(x.second);
     }
     uint32_t n_tiles = 0;
     uint64_t total_sites = 0;
@@ -715,7 +754,121 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         max_E = std::max(max_E, jobs[c].g.S * jobs[c].g.M * jobs[c].g.M);
     }
     const uint32_t count_tile = count_tile_for(total_sites);
+    std::vector<uint32_t> tile0v(n);
+    for (int c = 0; c < n; ++c) {
+        tile0v[c] = n_tiles;
+        n_tiles += count_tiles((uint32_t)jobs[c].g.N, count_tile);
+    }
+
+    // The device work of the call is fixed by the arena layout and the launches:
+    // a call of a structure seen before replays the graph recorded for it, with
+    // only the uploaded block (descriptors, tasks, targets) new.
+    int dev = 0;
+    PYHEA_HIP(hipGetDevice(&dev));
+    std::vector<int64_t> key = {dev, n, (int64_t)off, (int64_t)x_end, (int64_t)y_begin, (int64_t)y_end,
+                                (int64_t)o_descs, (int64_t)o_tasks, (int64_t)o_tile0, (int64_t)o_bad, n_tiles,
+                                count_tile, max_E};
+    for (const Launch &L : launches)
+        key.insert(key.end(), {L.first, L.count, L.store, L.M, L.S, L.B, L.W, L.bal, L.K, L.CH, L.lds});
+    ChainPlan *plan = nullptr;
+    if (graphs_enabled()) PYHEA_HIP(chain_plan(key, off, &plan));
+    std::unique_lock<std::mutex> plan_lock;
+    DeviceBuffer arena;
+    arena.stream = stream;
+    char *base;
+    if (plan) {
+        plan_lock = std::unique_lock<std::mutex>(plan->mu);
+        base = (char *)plan->arena;
+    } else {
+        PYHEA_HIP(pool_alloc(&arena.ptr, off, stream));
+        base = (char *)arena.ptr;
+    }
+
+    const CountTask *tasks = nullptr;
+    const uint32_t *tile0 = nullptr;
+    const ChainDesc *ddev = nullptr;
+    auto rebase = [&](char *b) {
+        base = b;
+        tasks = (const CountTask *)(base + o_tasks);
+        tile0 = (const uint32_t *)(base + o_tile0);
+        ddev = (const ChainDesc *)(base + o_descs);
+    };
+    rebase(base);
+
+    // the device work after the upload: zeroed read-back block; initial pair counts
+    // of every chain's configuration in one launch, then the ratio tables from
+    // them (an invalid chain is marked and skipped); the chains, one launch per
+    // group, groups side by side on auxiliary streams; the states' final
+    // objective; a fresh recount of every final configuration
+    auto device_work = [&](hipStream_t s, const hipStream_t *aux_set) -> hipError_t {
+        hipError_t e;
+        if ((e = launch_zero_i32((int32_t *)base, (int64_t)(x_end / 4), s)) != hipSuccess) return e;
+        if ((e = launch_count_tasks(tasks, tile0, n, n_tiles, count_tile, max_E, s)) != hipSuccess) return e;
+        if ((e = launch_chain_ratio(ddev, n, (const int32_t *)(base + o_bad), s)) != hipSuccess) return e;
+        {
+            Fork fork;
+            if ((e = fork.begin(s, (int)launches.size(), aux_set)) != hipSuccess) return e;
+            for (size_t l = 0; l < launches.size(); ++l) {
+                const Launch &L = launches[l];
+                hipStream_t ls = fork.stream((int)l);
+                if (L.store == kStoreGlobal && (e = launch_pad_fill(ddev + L.first, L.count, ls)) != hipSuccess)
+                    return e;
+                if ((e = launch_mc(ddev + L.first, L.count, L.store, L.M, L.S, L.B, L.W, L.bal, L.K, L.CH, L.lds,
+                                   INT_MAX, ls)) != hipSuccess)
+                    return e;
+                if (L.store == kStoreGlobal && (e = launch_pad_drain(ddev + L.first, L.count, ls)) != hipSuccess)
+                    return e;
+            }
+            if ((e = fork.end()) != hipSuccess) return e;
+        }
+        if ((e = launch_final_objective(ddev, n, s)) != hipSuccess) return e;
+        return launch_count_tasks(tasks + n, tile0, n, n_tiles, count_tile, max_E, s);
+    };
+    if (plan && !plan->exec) {
+        if (plan->failed || record_plan(plan, device_work) != hipSuccess) {
+            plan->failed = true;
+            // recording refused (now or before): this call, and later calls of the
+            // structure, run eagerly
+            (void)hipGetLastError();
+            plan_lock.unlock();
+            plan = nullptr;
+            PYHEA_HIP(pool_alloc(&arena.ptr, off, stream));
+            rebase((char *)arena.ptr);
+        }
+    }
+
+    // block Y on the host: targets, chain descriptors (ordered by launch group), count tasks
+    std::vector<char> hy(y_end - y_begin, 0);
+    auto hy_at = [&](size_t o) { return hy.data() + (o - y_begin); };
+    for (int c = 0; c < n; ++c)
+        std::memcpy(hy_at(o_target) + eoff[c] * 8, jobs[c].target.data(), jobs[c].target.size() * 8);
     {
+        ChainDesc *hd = (ChainDesc *)hy_at(o_descs);
+        for (int c = 0; c < n; ++c) {
+            const ChainJob &j = jobs[c];
+            ChainDesc &d = hd[pos[c]];
+            std::memset(&d, 0, sizeof(d));
+            fill_chain_geometry(j.g, &d);
+            d.seed = j.params.seed;
+            d.chain_id = j.params.chain_id;
+            d.B = j.params.cand_per_step;
+            d.n_trials = j.params.n_trials;
+            d.mode = j.params.commit_mode;
+            d.depth_limit = j.params.depth_limit;
+            d.tau = j.params.accept_tol;
+            for (int k = 0; k < kMaxShells; ++k) d.w[k] = k < j.g.S ? j.weight[k] : 0.0;
+            d.species = j.species_dev;
+            d.pad_global = shape[c].store == kStoreGlobal ? (int8_t *)(base + o_pad[c]) : nullptr;
+            d.R = (const double *)(base + o_R) + eoff[c];
+            d.target = (const double *)(base + o_target) + eoff[c];
+            d.counts = (int32_t *)(base + o_counts) + eoff[c];
+            d.log = j.log_dev;
+            d.log_cap = j.log_dev ? j.log_cap : 0;
+            d.state = (ChainState *)(base + o_state) + c;
+            d.store = shape[c].store;
+            d.lds_bytes = shape[c].lds;
+            d.sym = symmetric_target(j.target.data(), j.g.S, j.g.M);
+        }
         CountTask *ht = (CountTask *)hy_at(o_tasks);
         uint32_t *t0 = (uint32_t *)hy_at(o_tile0);
         for (int c = 0; c < n; ++c) {
@@ -727,41 +880,19 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
             b = a;
             b.counts = (int32_t *)(base + o_recount) + eoff[c];
             b.bad = (int32_t *)(base + o_bad2) + c;
-            t0[c] = n_tiles;
-            n_tiles += count_tiles((uint32_t)jobs[c].g.N, count_tile);
+            t0[c] = tile0v[c];
         }
     }
-    PYHEA_HIP(launch_zero_i32((int32_t *)base, (int64_t)(x_end / 4), stream));
-    PYHEA_HIP(hipMemcpyAsync(base + y_begin, hy.data(), hy.size(), hipMemcpyHostToDevice, stream));
-    const CountTask *tasks = (const CountTask *)(base + o_tasks);
-    const uint32_t *tile0 = (const uint32_t *)(base + o_tile0);
-
-    // initial pair counts of every chain's configuration, in one launch, then the
-    // ratio tables from them on the device (an invalid chain is marked and skipped)
-    PYHEA_HIP(launch_count_tasks(tasks, tile0, n, n_tiles, count_tile, max_E, stream));
-    const ChainDesc *ddev = (const ChainDesc *)(base + o_descs);
-    PYHEA_HIP(launch_chain_ratio(ddev, n, (const int32_t *)(base + o_bad), stream));
+    bool replayed = false;
+    if (plan) {
+        PYHEA_HIP(hipMemcpyAsync(base + y_begin, hy.data(), hy.size(), hipMemcpyHostToDevice, stream));
+        PYHEA_HIP(hipGraphLaunch(plan->exec, stream));
+        replayed = true;
+    } else {
+        PYHEA_HIP(hipMemcpyAsync(base + y_begin, hy.data(), hy.size(), hipMemcpyHostToDevice, stream));
+        PYHEA_HIP(device_work(stream, nullptr));
+    }
     std::vector<char> hx(x_end);
-
-    // the chains: one launch per group, groups side by side on auxiliary streams
-    {
-        Fork fork;
-        PYHEA_HIP(fork.begin(stream, (int)launches.size()));
-        for (size_t l = 0; l < launches.size(); ++l) {
-            const Launch &L = launches[l];
-            hipStream_t s = fork.stream((int)l);
-            if (L.store == kStoreGlobal) PYHEA_HIP(launch_pad_fill(ddev + L.first, L.count, s));
-            PYHEA_HIP(
-                launch_mc(ddev + L.first, L.count, L.store, L.M, L.S, L.B, L.W, L.bal, L.K, L.CH, L.lds, INT_MAX, s));
-            if (L.store == kStoreGlobal) PYHEA_HIP(launch_pad_drain(ddev + L.first, L.count, s));
-        }
-        PYHEA_HIP(fork.end());
-    }
-
-    // results: states with the final objective, maintained counts, and a fresh
-    // recount of every final configuration
-    PYHEA_HIP(launch_final_objective(ddev, n, stream));
-    PYHEA_HIP(launch_count_tasks(tasks + n, tile0, n, n_tiles, count_tile, max_E, stream));
     PYHEA_HIP(hipMemcpyAsync(hx.data(), base, x_end, hipMemcpyDeviceToHost, stream));
     PYHEA_HIP(hipStreamSynchronize(stream));
     const int32_t *cnt = (const int32_t *)(hx.data() + o_counts);
@@ -794,6 +925,7 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         s.log_len = jobs[c].log_dev ? std::min(s.commits, jobs[c].log_cap) : 0;
         s.shape = shape_code(shape[c]);
         s.shape_measured = measured[c];
+        s.graph = replayed ? 1 : 0;
         if (final_counts) (*final_counts)[c] = c64;
     }
     if (first_invalid >= 0) {
