@@ -361,25 +361,46 @@ def _params_block(params_list):
     return np.frombuffer(raw, dtype=np.uint8).copy()   # aligned, owned
 
 
-def pyhea_mc_batch(problems, species, offsets, params_list, log=None, log_offsets=None,
+class BatchPack:
+    """The chains of a batched call marshalled once into the C structures
+    (lattices, objectives, parameters), for callers that repeat a batch; pass
+    it to pyhea_mc_batch in place of the problem and parameter lists."""
+
+    def __init__(self, problems, params_list):
+        self.n = len(problems)
+        if len(params_list) != self.n:
+            raise ValueError("one parameter set per problem")
+        self.lat, self.obj, self.block = _batch_descriptors(problems)
+        self.pars = _params_block(params_list)
+        a = np.where(self.lat["lattice"] == FCC, 4, 2).astype(np.int64)
+        self.sizes = a * self.lat["L"].astype(np.int64).prod(axis=1)
+
+
+def pack_batch(problems, params_list) -> BatchPack:
+    return BatchPack(problems, params_list)
+
+
+def pyhea_mc_batch(problems, species, offsets, params_list=None, log=None, log_offsets=None,
                    stream=None):
     """Many chains in one call.  problems: list of (lattice, L, M, S, target,
-    weight); species: device int8, chains concatenated; offsets: [n+1] int64.
-    Returns the per-chain stats as a numpy structured array (fields of
-    pyhea_mc_stats: stats[i]["F"], ...)."""
+    weight) with params_list, or a BatchPack; species: device int8, chains
+    concatenated; offsets: [n+1] int64.  Returns the per-chain stats as a
+    numpy structured array (fields of pyhea_mc_stats: stats[i]["F"], ...)."""
     import torch
-    n = len(problems)
-    if len(params_list) != n:
-        raise ValueError("one parameter set per problem")
-    lat, obj, block = _batch_descriptors(problems)
-    pars = _params_block(params_list)
+    if isinstance(problems, BatchPack):
+        if params_list is not None:
+            raise ValueError("a BatchPack carries its parameters")
+        pack = problems
+    else:
+        if params_list is None:
+            raise ValueError("one parameter set per problem")
+        pack = BatchPack(problems, params_list)
+    n = pack.n
     stats = np.zeros(n, dtype=_STATS_DTYPE)
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
     loff = None if log_offsets is None else np.ascontiguousarray(np.asarray(log_offsets, np.int64))
     # every chain's slice must hold exactly its sites, and the slices must tile species
-    a = np.where(lat["lattice"] == FCC, 4, 2).astype(np.int64)
-    sizes = a * lat["L"].astype(np.int64).prod(axis=1)
-    if off.shape != (n + 1,) or off[0] != 0 or not np.array_equal(np.diff(off), sizes):
+    if off.shape != (n + 1,) or off[0] != 0 or not np.array_equal(np.diff(off), pack.sizes):
         raise ValueError("offsets: need n+1 values from 0 whose differences are each chain's site count")
     _need(species, int(off[-1]), "species")
     if log is not None:
@@ -388,10 +409,9 @@ def pyhea_mc_batch(problems, species, offsets, params_list, log=None, log_offset
         if loff is None or loff.shape != (n + 1,) or loff[0] != 0 or np.any(np.diff(loff) < 0) \
                 or loff[-1] > log.shape[0]:
             raise ValueError("log_offsets: need n+1 non-decreasing values from 0 within the log's rows")
-    _check(lib().pyhea_mc_batch(n, _hptr(lat), _hptr(obj), _hptr(pars), _dptr(species, torch.int8), _hptr(off),
-                                _dptr(log, torch.int32) if log is not None else None,
+    _check(lib().pyhea_mc_batch(n, _hptr(pack.lat), _hptr(pack.obj), _hptr(pack.pars), _dptr(species, torch.int8),
+                                _hptr(off), _dptr(log, torch.int32) if log is not None else None,
                                 _hptr(loff), _hptr(stats), _stream(stream)))
-    del block
     return stats
 
 

@@ -536,6 +536,50 @@ pyhea_status probe_launch(const ChainJob &j, int n_chains, int lds_budget, const
 
 namespace {
 
+// Page-locked host staging for a chain call's upload and read-back: copies
+// from and to it are single DMA transfers, and the upload returns at once.
+// Buffers are leased from a pool and kept until exit.  A lease is returned
+// only after its stream has drained, so no copy still reads or writes a
+// buffer the next call fills.
+struct PinnedBuf {
+    char *p = nullptr;
+    size_t cap = 0;
+};
+std::mutex g_pin_mu;
+auto *g_pin_free = new std::vector<PinnedBuf>();
+
+struct PinnedLease {
+    PinnedBuf b;
+    hipStream_t stream = nullptr;
+    bool drained = false;
+    ~PinnedLease() {
+        if (!b.p) return;
+        if (!drained) (void)hipStreamSynchronize(stream);
+        std::lock_guard<std::mutex> lock(g_pin_mu);
+        g_pin_free->push_back(b);
+    }
+};
+
+hipError_t pinned_lease(size_t bytes, hipStream_t stream, PinnedLease *out) {
+    out->stream = stream;
+    {
+        std::lock_guard<std::mutex> lock(g_pin_mu);
+        for (size_t i = 0; i < g_pin_free->size(); ++i)
+            if ((*g_pin_free)[i].cap >= bytes) {
+                out->b = (*g_pin_free)[i];
+                g_pin_free->erase(g_pin_free->begin() + (long)i);
+                return hipSuccess;
+            }
+    }
+    const size_t cap = std::max<size_t>((bytes + (size_t(1) << 20) - 1) & ~((size_t(1) << 20) - 1), size_t(1) << 20);
+    void *p = nullptr;
+    const hipError_t e = hipHostMalloc(&p, cap, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    out->b.p = (char *)p;
+    out->b.cap = cap;
+    return hipSuccess;
+}
+
 // Recorded device work of chain calls: a persistent arena and the graph that
 // runs a call's launches on it (run_chains).  A structure is recorded the
 // second time it is seen, so one-off calls never pay for recording.  Plans are
@@ -837,9 +881,15 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         }
     }
 
-    // block Y on the host: targets, chain descriptors (ordered by launch group), count tasks
-    std::vector<char> hy(y_end - y_begin, 0);
-    auto hy_at = [&](size_t o) { return hy.data() + (o - y_begin); };
+    // block Y on the host: targets, chain descriptors (ordered by launch group), count
+    // tasks; staged with the read-back block X in one page-locked lease
+    const size_t ny = y_end - y_begin;
+    PinnedLease lease;
+    PYHEA_HIP(pinned_lease(ny + align256(x_end), stream, &lease));
+    char *hyp = lease.b.p;
+    char *hxp = lease.b.p + ny;
+    std::memset(hyp, 0, ny);
+    auto hy_at = [&](size_t o) { return hyp + (o - y_begin); };
     for (int c = 0; c < n; ++c)
         std::memcpy(hy_at(o_target) + eoff[c] * 8, jobs[c].target.data(), jobs[c].target.size() * 8);
     {
@@ -884,20 +934,19 @@ pyhea_status run_chains(std::vector<ChainJob> &jobs, pyhea_mc_stats *stats,
         }
     }
     bool replayed = false;
+    PYHEA_HIP(hipMemcpyAsync(base + y_begin, hyp, ny, hipMemcpyHostToDevice, stream));
     if (plan) {
-        PYHEA_HIP(hipMemcpyAsync(base + y_begin, hy.data(), hy.size(), hipMemcpyHostToDevice, stream));
         PYHEA_HIP(hipGraphLaunch(plan->exec, stream));
         replayed = true;
     } else {
-        PYHEA_HIP(hipMemcpyAsync(base + y_begin, hy.data(), hy.size(), hipMemcpyHostToDevice, stream));
         PYHEA_HIP(device_work(stream, nullptr));
     }
-    std::vector<char> hx(x_end);
-    PYHEA_HIP(hipMemcpyAsync(hx.data(), base, x_end, hipMemcpyDeviceToHost, stream));
+    PYHEA_HIP(hipMemcpyAsync(hxp, base, x_end, hipMemcpyDeviceToHost, stream));
     PYHEA_HIP(hipStreamSynchronize(stream));
-    const int32_t *cnt = (const int32_t *)(hx.data() + o_counts);
-    const int32_t *rec = (const int32_t *)(hx.data() + o_recount);
-    const ChainState *sts = (const ChainState *)(hx.data() + o_state);
+    lease.drained = true;
+    const int32_t *cnt = (const int32_t *)(hxp + o_counts);
+    const int32_t *rec = (const int32_t *)(hxp + o_recount);
+    const ChainState *sts = (const ChainState *)(hxp + o_state);
     if (final_counts) final_counts->assign(n, {});
     int first_invalid = -1;
     for (int c = 0; c < n; ++c) {

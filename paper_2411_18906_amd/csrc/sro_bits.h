@@ -28,6 +28,7 @@ struct BitDesc {
     // 0 .. Lzc - 2 whole, and layer Lzc - 1 for its first BCC layer only
     // (half_last = 1).  Otherwise Lzc = Lz.
     int32_t zpair, Lzs, Lzc, half_last;
+    int32_t al2;       // the batch starts on an even address (z-paired rows read 16 bytes at a time)
     int32_t nh;
     int32_t hstart[kMaxShells + 1];
     int32_t zk[kMaxShells];

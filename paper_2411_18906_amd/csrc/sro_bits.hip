@@ -262,6 +262,40 @@ __device__ __forceinline__ uint32_t onehot_plane(const uint32_t *Dg, int j) {
     }
 }
 
+// Eight consecutive 2-byte cells c0 .. c0 + 7 of a BCC row at byte address a
+// (2-byte aligned), as four dwords of two cells each, read with one 16-byte
+// load from the dword boundary at or below a and, when a is not on one, the
+// dword after it.  head_ok / tail_ok: the 2 bytes before a / after the eight
+// cells may be read (false only at the ends of the buffer); otherwise those
+// dwords are replaced by 2-byte reads of the cells' own bytes.
+struct __attribute__((packed, aligned(4))) Dw4 {
+    uint32_t x, y, z, w;
+};
+__device__ __forceinline__ void row_cells8(const uint8_t *a, bool head_ok, bool tail_ok, uint32_t u[4]) {
+    const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(a) & 3u);   // 0 or 2
+    const uint8_t *A = a - sh;
+    uint32_t w0, w1, w2, w3, w4 = 0;
+    if (sh == 0 || head_ok) {
+        const Dw4 v = *reinterpret_cast<const Dw4 *>(A);
+        w0 = v.x;
+        w1 = v.y;
+        w2 = v.z;
+        w3 = v.w;
+    } else {   // the first cell's bytes only, placed where the shift takes them from
+        w0 = (uint32_t)(*reinterpret_cast<const uint16_t *>(a)) << 16;
+        w1 = *reinterpret_cast<const uint32_t *>(A + 4);
+        w2 = *reinterpret_cast<const uint32_t *>(A + 8);
+        w3 = *reinterpret_cast<const uint32_t *>(A + 12);
+    }
+    if (sh != 0)
+        w4 = tail_ok ? *reinterpret_cast<const uint32_t *>(A + 16)
+                     : (uint32_t)(*reinterpret_cast<const uint16_t *>(A + 16));
+    u[0] = __builtin_amdgcn_alignbyte(w1, w0, sh);
+    u[1] = __builtin_amdgcn_alignbyte(w2, w1, sh);
+    u[2] = __builtin_amdgcn_alignbyte(w3, w2, sh);
+    u[3] = __builtin_amdgcn_alignbyte(w4, w3, sh);
+}
+
 // MaxW: the wavefronts per SIMD the register allocation aims for -- 4 for a
 // workgroup alone on its CU (registers spent on overlapping loads), 8 when
 // several workgroups share the CU.
@@ -406,6 +440,24 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
                 for (int gg = 0; gg < GF; ++gg) {
                     const int g = g0 + gg;
                     if (32 * cxc + 8 * g >= RS) continue;   // uniform
+                    const int c0 = 32 * cxc + 8 * g - 1;
+                    if (bd.zpair && bd.al2 && c0 >= 0 && c0 + 8 <= bd.Lx) {   // uniform: no wrap in the group
+                        // wide reads of both BCC rows; a row's bytes before / after the
+                        // group lie in the buffer unless the row opens / closes it
+                        const bool lo_first = kc == 0 && rowlo == 0, hi_first = kc == 0 && rowhi == 0;
+                        const uint32_t last = bd.N - 2u * (uint32_t)bd.Lx;
+                        const bool lo_last = kc == K - 1 && rowlo == last, hi_last = kc == K - 1 && rowhi == last;
+                        const bool tail = c0 + 8 < bd.Lx;
+                        uint32_t ul[4], uh[4];
+                        row_cells8(cfg + rowlo + 2u * (uint32_t)c0, c0 > 0 || !lo_first, tail || !lo_last, ul);
+                        row_cells8(cfg + rowhi + 2u * (uint32_t)c0, c0 > 0 || !hi_first, tail || !hi_last, uh);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            d[gg][2 * k] = perm(uh[k], ul[k], 0x05040100u);
+                            d[gg][2 * k + 1] = perm(uh[k], ul[k], 0x07060302u);
+                        }
+                        continue;
+                    }
 #pragma unroll
                     for (int m = 0; m < 8; ++m) {
                         int c = 32 * cxc + 8 * g + m - 1;
@@ -1212,6 +1264,7 @@ hipError_t launch_count_bits(const Geometry &g, const BitDesc &bd, int64_t K, co
     if (!f) return hipErrorInvalidValue;
     BitDesc b = bd;
     b.vec4 = !bd.zpair && bd.Lx % 4 == 0 && (reinterpret_cast<uintptr_t>(species) & 15) == 0 ? 1 : 0;
+    b.al2 = (reinterpret_cast<uintptr_t>(species) & 1) == 0 ? 1 : 0;
     return f(b, K, species, partial, counts, bad, tw, S_F, stream);
 }
 

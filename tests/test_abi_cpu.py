@@ -144,6 +144,15 @@ def test_binding_rejects_mis_sized_buffers_before_the_library():
                          [0, 2, 5])
     with pytest.raises(TypeError):    # consistent sizes reach the pointer check
         b.pyhea_mc_batch(probs, sp2, [0, N, N + N // 2], pars)
+    pack = b.pack_batch(probs, pars)  # the same checks through a packed batch
+    with pytest.raises(ValueError):
+        b.pyhea_mc_batch(pack, sp2, [0, N, N + N // 2 + 1])
+    with pytest.raises(ValueError):   # a pack carries its own parameters
+        b.pyhea_mc_batch(pack, sp2, [0, N, N + N // 2], pars)
+    with pytest.raises(TypeError):
+        b.pyhea_mc_batch(pack, sp2, [0, N, N + N // 2])
+    with pytest.raises(ValueError):   # lists need parameters
+        b.pyhea_mc_batch(probs, sp2, [0, N, N + N // 2])
     with pytest.raises(ValueError):
         b.pyhea_philox4x32_10(torch.zeros(4, 3, dtype=torch.int32), 1, torch.zeros(4, 3, dtype=torch.int32))
     with pytest.raises(ValueError):
@@ -194,5 +203,12 @@ def test_binding_wrappers_marshal_without_gpu(monkeypatch):
     b.pyhea_map_sites(b.FCC, L, M, S, (10.0, 10.0, 10.0), 0.5, xyz, sp[0], sp[1])
     b.pyhea_tune_measure(True)
     b.pyhea_tune_force_stream(0, 0)
+    b.pyhea_tune_graphs(True)
+    probs = [(b.FCC, L, M, S, tgt, w)] * 2
+    pars = [b.make_params(1, 0, 10), b.make_params(1, 1, 10)]
+    flat = sp[:2].reshape(-1)
+    b.pyhea_mc_batch(probs, flat, [0, N, 2 * N], pars)
+    b.pyhea_mc_batch(b.pack_batch(probs, pars), flat, [0, N, 2 * N])
     assert calls == ["pyhea_sro_eval_batch", "pyhea_sro_eval_batch_noalloc", "pyhea_map_sites",
-                     "pyhea_tune_measure", "pyhea_tune_force_stream"]
+                     "pyhea_tune_measure", "pyhea_tune_force_stream", "pyhea_tune_graphs",
+                     "pyhea_mc_batch", "pyhea_mc_batch"]

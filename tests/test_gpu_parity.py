@@ -139,6 +139,35 @@ def _batch_case(lattice, L, M, S, K):
         assert sf[k, 0] == S_o and sf[k, 1] == F_o
 
 
+@pytest.mark.parametrize("shift", [1, 2, 4])
+@pytest.mark.parametrize("L,M,S,K", [((31, 5, 3), 5, 3, 4), ((7, 3, 4), 4, 2, 5), ((15, 2, 2), 3, 1, 3),
+                                     ((23, 4, 5), 6, 3, 2)])
+def test_zpaired_bcc_any_alignment(L, M, S, K, shift):
+    """Odd-Lx BCC read through a batch that starts 1, 2 or 4 bytes past an
+    aligned address: wide row reads, their shifts and the guarded first and
+    last rows of the buffer, or the 2-byte reads an odd start falls back to."""
+    N = orc.n_sites(orc.BCC, L)
+    cfg = wl.iid_configs(N, M, K, seed=K + shift)
+    buf = torch.zeros(K * N + 8, dtype=torch.int8, device="cuda")
+    view = buf[shift:shift + K * N].view(K, N)
+    view.copy_(dev(cfg))
+    rng = np.random.default_rng(shift)
+    tgt = rng.uniform(-0.2, 0.2, (S, M, M))
+    w = rng.uniform(0.1, 1.0, S)
+    counts = torch.zeros((K, S, M, M), dtype=torch.int32, device="cuda")
+    SF = torch.zeros((K, 2), dtype=torch.float64, device="cuda")
+    pb.pyhea_sro_eval_batch(orc.BCC, L, M, S, view, counts, tgt, w, SF)
+    torch.cuda.synchronize()
+    c = counts.cpu().numpy()
+    sf = SF.cpu().numpy()
+    for k in range(K):
+        want = orc.counts(orc.BCC, L, M, S, cfg[k])
+        np.testing.assert_array_equal(c[k], want, err_msg=f"config {k}")
+        if (np.bincount(cfg[k], minlength=M) > 0).all():
+            _, _, S_o, F_o = orc.alpha_objective(orc.BCC, L, M, S, cfg[k], want, tgt, w)
+            assert sf[k, 0] == S_o and sf[k, 1] == F_o
+
+
 STREAM_CASES = [
     # (lattice, L, M, S, K): several configurations per persistent workgroup,
     # layer groups that divide Lz and ragged ones, a chunk 0 covering all layers
