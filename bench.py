@@ -455,6 +455,7 @@ def main():
     # not depend on the trial count when every chain of a call has the same)
     progress("first use: launch shapes and recorded graphs")
     for _ in range(2):
+        w = None
         if "chain" in legs:
             w = chain0.clone()
             pb.pyhea_mc_run(p.lattice, p.L, p.M, p.S, p.target, p.weight, w,
