@@ -359,9 +359,9 @@ namespace {
 // only in how commits are grouped cost the same between commits, and a short
 // segment cannot tell them apart.  Sets *ok false if the chain is invalid (the
 // real run reports it).
-constexpr int kProbeWarm = 48;
+constexpr int kProbeWarm = 64;
 constexpr int kProbeBase = 16;
-constexpr int kProbeSteps = 96;
+constexpr int kProbeSteps = 320;
 constexpr int kProbeReps = 3;
 constexpr double kProbeMargin = 0.03;
 
