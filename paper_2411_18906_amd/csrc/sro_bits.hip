@@ -441,20 +441,36 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
                     const int g = g0 + gg;
                     if (32 * cxc + 8 * g >= RS) continue;   // uniform
                     const int c0 = 32 * cxc + 8 * g - 1;
-                    if (bd.zpair && bd.al2 && c0 >= 0 && c0 + 8 <= bd.Lx) {   // uniform: no wrap in the group
-                        // wide reads of both BCC rows; a row's bytes before / after the
-                        // group lie in the buffer unless the row opens / closes it
+                    // the row's first group: the wrapped cell Lx - 1, then cells 0 .. 6
+                    const bool first = c0 == -1 && bd.Lx >= 10;
+                    if (bd.zpair && bd.al2 && (first || (c0 >= 0 && c0 + 8 <= bd.Lx))) {   // uniform
+                        // wide reads of both BCC rows (cells r0 .. r0 + 7); a row's bytes
+                        // before / after them lie in the buffer unless the row opens /
+                        // closes it
+                        const int r0 = first ? 0 : c0;
                         const bool lo_first = kc == 0 && rowlo == 0, hi_first = kc == 0 && rowhi == 0;
                         const uint32_t last = bd.N - 2u * (uint32_t)bd.Lx;
                         const bool lo_last = kc == K - 1 && rowlo == last, hi_last = kc == K - 1 && rowhi == last;
-                        const bool tail = c0 + 8 < bd.Lx;
+                        const bool tail = r0 + 8 < bd.Lx;
                         uint32_t ul[4], uh[4];
-                        row_cells8(cfg + rowlo + 2u * (uint32_t)c0, c0 > 0 || !lo_first, tail || !lo_last, ul);
-                        row_cells8(cfg + rowhi + 2u * (uint32_t)c0, c0 > 0 || !hi_first, tail || !hi_last, uh);
+                        row_cells8(cfg + rowlo + 2u * (uint32_t)r0, r0 > 0 || !lo_first, tail || !lo_last, ul);
+                        row_cells8(cfg + rowhi + 2u * (uint32_t)r0, r0 > 0 || !hi_first, tail || !hi_last, uh);
+                        if (first) {   // column m holds cell m - 1: the loaded cells move up one column
+                            const uint32_t cl = 2u * (uint32_t)(bd.Lx - 1);
+                            const uint32_t a = *reinterpret_cast<const uint16_t *>(cfg + (rowlo + cl));
+                            const uint32_t b = *reinterpret_cast<const uint16_t *>(cfg + (rowhi + cl));
+                            d[gg][0] = a | (b << 16);
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            d[gg][2 * k] = perm(uh[k], ul[k], 0x05040100u);
-                            d[gg][2 * k + 1] = perm(uh[k], ul[k], 0x07060302u);
+                            for (int k = 0; k < 4; ++k) {
+                                d[gg][2 * k + 1] = perm(uh[k], ul[k], 0x05040100u);
+                                if (k < 3) d[gg][2 * k + 2] = perm(uh[k], ul[k], 0x07060302u);
+                            }
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                d[gg][2 * k] = perm(uh[k], ul[k], 0x05040100u);
+                                d[gg][2 * k + 1] = perm(uh[k], ul[k], 0x07060302u);
+                            }
                         }
                         continue;
                     }
