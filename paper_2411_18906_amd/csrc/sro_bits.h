@@ -29,6 +29,7 @@ struct BitDesc {
     // (half_last = 1).  Otherwise Lzc = Lz.
     int32_t zpair, Lzs, Lzc, half_last;
     int32_t al2;       // the batch starts on an even address (z-paired rows read 16 bytes at a time)
+    int32_t hx, hy, hz;  // border of the layout: columns and rows each side, layers above
     int32_t nh;
     int32_t hstart[kMaxShells + 1];
     int32_t zk[kMaxShells];
@@ -66,7 +67,7 @@ hipError_t launch_count_stream(const Geometry &g, const StreamDesc &sd, int64_t 
                                int32_t *counts, int32_t *bad, const double *tw, double *S_F, hipStream_t stream);
 
 // Fills bd; false if the bit-sliced kernel does not cover this geometry (it
-// covers FCC and BCC for shells whose neighbours lie at most one cell away;
+// covers FCC and BCC for shells whose neighbours lie at most two cells away;
 // four-site cells pair BCC cells along x, or along z when Lx is odd).
 // K is the number of configurations of the launch: few configurations are
 // split along z over more workgroups.  With split > 1, a configuration whose

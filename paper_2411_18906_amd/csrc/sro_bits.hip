@@ -1,15 +1,16 @@
 // Bit-sliced full SRO evaluation (Sec. 4.3, Eq. 2) for lattices laid out as
-// cells of four sites: FCC, and BCC with an even number of cells along x (two
-// BCC cells along x form one four-site cell; see fill_bit_desc).
+// cells of four sites: FCC, and BCC (two BCC cells along x, or along z when
+// the number of cells along x is odd, form one four-site cell; see
+// fill_bit_desc).
 //
 // One workgroup counts a range of z-layers of one configuration:
 //  1. Conversion.  Per sublattice b and species j < M-1 a layer becomes a flat
-//     bit array with a one-cell periodic border: bit fy * RS + fx (RS = Lx + 2)
-//     holds cell ((fx - 1) mod Lx, (fy - 1) mod Ly).  A lane converts one padded
-//     row: each cell is one dword (4 sublattice bytes), a v_perm lookup maps
-//     species ids to one-hot bytes, 8 cells are merged per byte lane with
-//     shift-or, and a 4x4 byte transpose yields 32-position bit rows that are
-//     OR-ed into LDS.  The M-1 species planes are interleaved word by word:
+//     bit array with a periodic border of hx columns and hy rows (one each,
+//     two for BCC shell 4): bit fy * RS + fx (RS = Lx + 2 hx) holds cell
+//     ((fx - hx) mod Lx, (fy - hy) mod Ly).  A lane converts one padded row:
+//     each cell is one dword (4 sublattice bytes), converted eight at a time
+//     through their species' binary digits, and a 4x4 byte transpose yields
+//     32-position bit rows (one-hot per species) that are OR-ed into LDS.  The M-1 species planes are interleaved word by word:
 //     dword ((layer * 4 + b) * PW + word) * (M - 1) + j.
 //  2. Counting.  For a half-offset d (one of each +-d pair) from sublattice b to
 //     b' with cell delta (dx, dy, dz), the neighbour bits of a 32-bit word are a
@@ -314,7 +315,7 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
     const int chunk = blockIdx.x;
     const int z0 = chunk * bd.ZC;
     const int nz = min(bd.ZC, bd.Lzc - z0);  // centre layers of this workgroup
-    const int nl = nz + 1;                   // plus the next layer (dz in {0, 1})
+    const int nl = nz + bd.hz;               // plus the layers above (dz in 0 .. hz)
     const int PW = bd.PW;
     const int RS = bd.RS;
     const int nplane = nl * 4 * PW * P;      // plane dwords (a multiple of 4)
@@ -338,13 +339,15 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
     for (int w = threadIdx.x; w < bd.LW; w += blockDim.x) {
         const int x0 = 32 * w;
         uint32_t m = 0xFFFFFFFFu;
-        const int lo = RS - x0;                  // bits below lo lie in row 0
+        const int lo = bd.hy * RS - x0;          // bits below lo lie in the border rows below
         if (lo > 0) m &= lo >= 32 ? 0u : (0xFFFFFFFFu << lo);
-        const int hi = (bd.Ly + 1) * RS - x0;    // bits from hi on lie in row Ly + 1 or beyond
+        const int hi = (bd.Ly + bd.hy) * RS - x0;   // bits from hi on lie in the border rows above
         if (hi < 32) m &= hi <= 0 ? 0u : (0xFFFFFFFFu >> (32 - hi));
         const int c0 = x0 % RS;                  // column of bit 0
-        for (int t = (RS - c0) % RS; t < 32; t += RS) m &= ~(1u << t);               // column 0
-        for (int t = (2 * RS - 1 - c0) % RS; t < 32; t += RS) m &= ~(1u << t);       // column RS - 1
+        for (int e = 0; e < bd.hx; ++e) {        // border columns e and RS - 1 - e
+            for (int t = (RS + e - c0) % RS; t < 32; t += RS) m &= ~(1u << t);
+            for (int t = (2 * RS - 1 - e - c0) % RS; t < 32; t += RS) m &= ~(1u << t);
+        }
         cmask[w] = m;
     }
     __syncthreads();
@@ -353,17 +356,18 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
     const uint8_t *cfg = reinterpret_cast<const uint8_t *>(species) + kc * (int64_t)bd.N;
     uint32_t badacc = 0;
     const uint32_t kBad = (0x80u - M) * 0x01010101u;   // byte + kBad has bit 7 set iff byte >= M (bytes < 0x80)
-    const int rows = bd.Ly + 2;
+    const int rows = bd.Ly + 2 * bd.hy;
     const int nitems = nl * rows;
     const double inv_rows = 1.0 / rows;
 #pragma unroll 1
     for (int it = threadIdx.x; it < nitems; it += blockDim.x) {
         const int ll = qdiv(it, inv_rows);
         const int fy = it - ll * rows;
-        int cy = fy - 1;
-        cy = cy < 0 ? bd.Ly - 1 : (cy >= bd.Ly ? 0 : cy);
+        int cy = fy - bd.hy;   // in -hy .. Ly + hy - 1
+        cy = cy < 0 ? cy + bd.Ly : (cy >= bd.Ly ? cy - bd.Ly : cy);
+        cy = cy < 0 || cy >= bd.Ly ? 0 : cy;   // one row (Ly = 1 < hy)
         int cz = z0 + ll;
-        if (cz >= bd.Lz) cz -= bd.Lz;
+        while (cz >= bd.Lz) cz -= bd.Lz;
         const uint32_t rowoff = (uint32_t)((cz * bd.Ly + cy) * bd.Lx) * 4u;
         // z-paired BCC: the row's two BCC rows (layers 2 cz and 2 cz + 1 mod Lzs), 2 Lx bytes each
         uint32_t rowlo = 0, rowhi = 0;
@@ -429,8 +433,8 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
                     __builtin_amdgcn_sched_barrier(0);   // one group of eight columns at a time
                 }
             } else {
-            // padded column pos holds cell (pos - 1) mod Lx; columns past the row
-            // end read cell 0 and are masked below, so every load is in bounds.
+            // padded column pos holds cell (pos - hx) mod Lx; columns past the row
+            // end read some cell and are masked below, so every load is in bounds.
             // GF groups of 8 loads are issued before any of them is used.
             constexpr int GF = MaxW <= 4 ? 4 : 2;
 #pragma unroll
@@ -440,7 +444,7 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
                 for (int gg = 0; gg < GF; ++gg) {
                     const int g = g0 + gg;
                     if (32 * cxc + 8 * g >= RS) continue;   // uniform
-                    const int c0 = 32 * cxc + 8 * g - 1;
+                    const int c0 = 32 * cxc + 8 * g - bd.hx;
                     // the row's first group: the wrapped cell Lx - 1, then cells 0 .. 6
                     const bool first = c0 == -1 && bd.Lx >= 10;
                     if (bd.zpair && bd.al2 && (first || (c0 >= 0 && c0 + 8 <= bd.Lx))) {   // uniform
@@ -455,29 +459,30 @@ count_bits_kernel(BitDesc bd, int64_t K, const int8_t *__restrict__ species, int
                         uint32_t ul[4], uh[4];
                         row_cells8(cfg + rowlo + 2u * (uint32_t)r0, r0 > 0 || !lo_first, tail || !lo_last, ul);
                         row_cells8(cfg + rowhi + 2u * (uint32_t)r0, r0 > 0 || !hi_first, tail || !hi_last, uh);
+                        uint32_t e[8];   // cells r0 .. r0 + 7 as four-site dwords
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            e[2 * k] = perm(uh[k], ul[k], 0x05040100u);
+                            e[2 * k + 1] = perm(uh[k], ul[k], 0x07060302u);
+                        }
+                        uint32_t w0 = 0;
                         if (first) {   // column m holds cell m - 1: the loaded cells move up one column
                             const uint32_t cl = 2u * (uint32_t)(bd.Lx - 1);
                             const uint32_t a = *reinterpret_cast<const uint16_t *>(cfg + (rowlo + cl));
                             const uint32_t b = *reinterpret_cast<const uint16_t *>(cfg + (rowhi + cl));
-                            d[gg][0] = a | (b << 16);
-#pragma unroll
-                            for (int k = 0; k < 4; ++k) {
-                                d[gg][2 * k + 1] = perm(uh[k], ul[k], 0x05040100u);
-                                if (k < 3) d[gg][2 * k + 2] = perm(uh[k], ul[k], 0x07060302u);
-                            }
-                        } else {
-#pragma unroll
-                            for (int k = 0; k < 4; ++k) {
-                                d[gg][2 * k] = perm(uh[k], ul[k], 0x05040100u);
-                                d[gg][2 * k + 1] = perm(uh[k], ul[k], 0x07060302u);
-                            }
+                            w0 = a | (b << 16);
                         }
+#pragma unroll
+                        for (int m = 0; m < 8; ++m) d[gg][m] = first ? (m == 0 ? w0 : e[m - 1]) : e[m];
                         continue;
                     }
 #pragma unroll
                     for (int m = 0; m < 8; ++m) {
-                        int c = 32 * cxc + 8 * g + m - 1;
-                        c = c < 0 ? bd.Lx - 1 : (c >= bd.Lx ? 0 : c);
+                        // padded column pos holds cell (pos - hx) mod Lx; columns past
+                        // the padded row read some cell and are masked below
+                        int c = 32 * cxc + 8 * g + m - bd.hx;
+                        c = c < 0 ? c + bd.Lx : (c >= bd.Lx ? c - bd.Lx : c);
+                        c = c < 0 || c >= bd.Lx ? 0 : c;   // past the padded row, or a row of one cell
                         if (bd.zpair) {   // uniform: sublattices 0, 1 from the lower BCC row, 2, 3 from the upper
                             const uint32_t a = *reinterpret_cast<const uint16_t *>(cfg + (rowlo + 2u * (uint32_t)c));
                             const uint32_t b = *reinterpret_cast<const uint16_t *>(cfg + (rowhi + 2u * (uint32_t)c));
@@ -1099,7 +1104,7 @@ hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_
                      int32_t *bad, const double *tw, double *S_F, hipStream_t stream) {
     const int P = M - 1;
     const int NV = S * Pairs<M>::NP + P;
-    const size_t lds = ((size_t)(bd.ZC + 1) * 4 * P * bd.PW + ((bd.LW + 3) & ~3) + NV * 64 + NV + 1 + 8 * bd.nh + 1 +
+    const size_t lds = ((size_t)(bd.ZC + bd.hz) * 4 * P * bd.PW + ((bd.LW + 3) & ~3) + NV * 64 + NV + 1 + 8 * bd.nh + 1 +
                         3 * S * M * M + 2 * S * M + 2) * 4;
     const bool lone = bd.threads > 512;   // one workgroup per CU
     using KernelFn = void (*)(BitDesc, int64_t, const int8_t *, int32_t *, int32_t *, int32_t *, const double *,
@@ -1177,7 +1182,7 @@ static void four_site_target(const Geometry &g, int axis, int b, int t, int dc[3
 
 bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitDesc *bd) {
     std::memset(bd, 0, sizeof(*bd));
-    if (g.halo != 1 || !pick(g.M, g.S)) return false;
+    if (!pick(g.M, g.S)) return false;
     // Cells of four sites: an FCC cell, or two BCC cells along x (site id
     // ((cz Ly + cy) Lx + cx) 2 + b is ((cz Ly + cy) (Lx/2) + cx/2) 4 + 2 (cx % 2) + b,
     // so an even-Lx BCC configuration is laid out as cells of four sublattices).
@@ -1206,6 +1211,27 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitD
         return false;
     }
     const int P = g.M - 1;
+    // the layout's border: every kept half-offset's target lies within hx cells
+    // along x, hy along y and 0 .. hz layers up (1 each for shells whose
+    // neighbours lie at most one cell away; 2 for BCC shell 4)
+    const int axis = zpair ? 2 : 0;
+    int hx = 1, hy = 1, hz = 1;
+    for (int t = g.zstart[0]; t < g.zstart[g.S]; ++t) {
+        const int dx = g.off[t][0], dy = g.off[t][1], dz = g.off[t][2];
+        if (!(dz > 0 || (dz == 0 && (dy > 0 || (dy == 0 && dx > 0))))) continue;
+        for (int b = 0; b < 4; ++b) {
+            int dc[3], bt;
+            four_site_target(g, axis, b, t, dc, &bt);
+            if (dc[2] < 0) return false;
+            hx = std::max(hx, std::abs(dc[0]));
+            hy = std::max(hy, std::abs(dc[1]));
+            hz = std::max(hz, dc[2]);
+        }
+    }
+    if (hx > 2 || hy > 2 || hz > 2) return false;
+    bd->hx = hx;
+    bd->hy = hy;
+    bd->hz = hz;
     bd->Lx = Lx4;
     bd->Ly = g.L[1];
     bd->Lz = Lz4;
@@ -1213,13 +1239,13 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitD
     bd->Lzs = g.L[2];
     bd->Lzc = Lzc;
     bd->half_last = half_last;
-    bd->RS = Lx4 + 2;
-    const int bits = (g.L[1] + 2) * bd->RS;
+    bd->RS = Lx4 + 2 * hx;
+    const int bits = (g.L[1] + 2 * hy) * bd->RS;
     bd->LW = (bits + 31) / 32;
-    bd->PADW = (bd->RS + 2 + 31) / 32 + 1;
+    bd->PADW = (hy * bd->RS + hx + 1 + 31) / 32 + 1;
     bd->PW = bd->LW + 2 * bd->PADW;
-    bd->cw0 = bd->RS / 32;
-    bd->NCW = ((g.L[1] + 1) * bd->RS - 1) / 32 - bd->cw0 + 1;
+    bd->cw0 = hy * bd->RS / 32;
+    bd->NCW = ((g.L[1] + hy) * bd->RS - 1) / 32 - bd->cw0 + 1;
     bd->nchx = (bd->RS + 31) / 32;
     bd->N = (uint32_t)g.N;
     const int np = P * (P + 1) / 2;
@@ -1231,9 +1257,9 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitD
     const int per_layer = 4 * P * bd->PW * 4;
     // split > 1: a configuration whose layers would take more than 1/split of a
     // CU's LDS is cut along z so that `split` workgroups share each CU
-    const int budget = split > 1 && fixed + (Lzc + 1) * per_layer > lds_budget / split ? lds_budget / split
-                                                                                        : lds_budget;
-    int zc = (budget - fixed) / per_layer - 1;
+    const int budget = split > 1 && fixed + (Lzc + hz) * per_layer > lds_budget / split ? lds_budget / split
+                                                                                         : lds_budget;
+    int zc = (budget - fixed) / per_layer - hz;
     if (zc < 1) return false;
     zc = std::min(zc, Lzc);
     zc = (Lzc + (Lzc + zc - 1) / zc - 1) / ((Lzc + zc - 1) / zc);
@@ -1244,7 +1270,7 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitD
     bd->nchunks = (Lzc + zc - 1) / zc;
     // a workgroup that needs more than half the LDS runs alone on its CU: give it
     // 16 wavefronts so the CU still has latency to hide behind
-    bd->threads = fixed + (zc + 1) * per_layer > lds_budget / 2 ? 1024 : 512;
+    bd->threads = fixed + (zc + hz) * per_layer > lds_budget / 2 ? 1024 : 512;
     // half offsets ordered by shell
     int nh = 0;
     for (int k = 0; k < g.S; ++k) {
@@ -1255,9 +1281,7 @@ bool fill_bit_desc(const Geometry &g, int lds_budget, int64_t K, int split, BitD
             if (!keep) continue;
             for (int b = 0; b < 4; ++b) {
                 int dc[3], bt;
-                four_site_target(g, zpair ? 2 : 0, b, t, dc, &bt);
-                // the layout covers cell deltas of -1..1 along x and y, 0..1 along z
-                if (dc[0] < -1 || dc[0] > 1 || dc[1] < -1 || dc[1] > 1 || dc[2] < 0 || dc[2] > 1) return false;
+                four_site_target(g, axis, b, t, dc, &bt);
                 // plane word of the neighbour: layer +dz, sublattice bt, bit shift s
                 const int s = dc[1] * bd->RS + dc[0];
                 const int q = s >= 0 ? s / 32 : -((-s + 31) / 32);
@@ -1279,7 +1303,7 @@ hipError_t launch_count_bits(const Geometry &g, const BitDesc &bd, int64_t K, co
     LaunchFn f = pick(g.M, g.S);
     if (!f) return hipErrorInvalidValue;
     BitDesc b = bd;
-    b.vec4 = !bd.zpair && bd.Lx % 4 == 0 && (reinterpret_cast<uintptr_t>(species) & 15) == 0 ? 1 : 0;
+    b.vec4 = !bd.zpair && bd.hx == 1 && bd.Lx % 4 == 0 && (reinterpret_cast<uintptr_t>(species) & 15) == 0 ? 1 : 0;
     b.al2 = (reinterpret_cast<uintptr_t>(species) & 1) == 0 ? 1 : 0;
     return f(b, K, species, partial, counts, bad, tw, S_F, stream);
 }

@@ -88,7 +88,7 @@ BATCH_SHAPES = [
     (orc.FCC, (40, 40, 40), 4, 2, 3), (orc.FCC, (33, 5, 7), 3, 4, 4), (orc.FCC, (1, 2, 3), 2, 1, 5),
     (orc.FCC, (70, 3, 6), 6, 2, 4), (orc.FCC, (2, 2, 2), 8, 2, 6), (orc.FCC, (7, 3, 2), 7, 1, 5),
     (orc.FCC, (6, 5, 4), 6, 4, 5), (orc.FCC, (64, 64, 64), 5, 3, 3),
-    # BCC with even Lx runs on the four-site-cell layout; shell 4 uses gathers
+    # BCC with even Lx runs on the four-site-cell layout
     (orc.BCC, (8, 8, 8), 5, 3, 20), (orc.BCC, (2, 3, 3), 3, 3, 7), (orc.BCC, (10, 4, 6), 6, 2, 9),
     (orc.BCC, (64, 32, 32), 4, 2, 3), (orc.BCC, (7, 4, 4), 3, 2, 5), (orc.BCC, (4, 4, 4), 4, 4, 4),
     # BCC with odd Lx: cells paired along z (even Lz), or along z over the
@@ -97,6 +97,11 @@ BATCH_SHAPES = [
     (orc.BCC, (9, 2, 7), 3, 3, 9), (orc.BCC, (33, 6, 5), 8, 2, 4), (orc.BCC, (5, 3, 2), 4, 3, 7),
     (orc.BCC, (7, 4, 6), 5, 2, 5), (orc.BCC, (3, 3, 1), 3, 1, 8), (orc.BCC, (31, 32, 32), 4, 2, 3),
     (orc.BCC, (5, 6, 9), 7, 3, 3),
+    # BCC shell 4 (neighbours up to two cells away): a border of two rows and
+    # two layers (and two columns for odd Lx), down to two-cell rows and columns
+    (orc.BCC, (8, 8, 8), 5, 4, 6), (orc.BCC, (6, 5, 7), 3, 4, 5), (orc.BCC, (5, 6, 6), 4, 4, 4),
+    (orc.BCC, (7, 4, 5), 6, 4, 3), (orc.BCC, (2, 2, 2), 3, 4, 4), (orc.BCC, (4, 2, 3), 4, 4, 4),
+    (orc.BCC, (3, 3, 2), 3, 4, 5), (orc.BCC, (16, 12, 10), 8, 4, 3),
     # counting order: a two-layer workgroup with 60-64 centre words per basis walks
     # them basis-major (padded to one wavefront), a one-layer workgroup layer-major;
     # the first three launches hold one of each
