@@ -334,7 +334,7 @@ def incremental_vs_full(pb, p, torch, out):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               f"(independent chains and batches shard across GPUs with no exchange).",
               file=sys.stderr)
         sys.exit(2)

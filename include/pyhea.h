@@ -52,7 +52,7 @@ typedef int32_t pyhea_status;
 #define PYHEA_EDEVICE (-3)    /* a HIP runtime call failed                     */
 #define PYHEA_EBUSY (-4)      /* serving: job not finished yet                 */
 #define PYHEA_ECANCELLED (-5) /* serving: job cancelled                        */
-#define PYHEA_ENOSYS (-6)     /* not supported in this build                   */
+#define PYHEA_ENOSYS (-6)     /* not supported by this library                 */
 #define PYHEA_ENOENT (-7)     /* serving: unknown job id                       */
 
 #define PYHEA_FCC 0

@@ -15,7 +15,7 @@ _pool = None
 
 
 def workers() -> int:
-    # a GPU machine grants this process a share of 16 CPUs, whatever os.cpu_count() shows
+    # at most 16 workers: the process may hold a share of 16 CPUs whatever os.cpu_count() shows
     return max(1, min(16, os.cpu_count() or 1))
 
 
