@@ -225,7 +225,7 @@ def serve(pb, wl, n_jobs, capacity_trials_per_s, load, budget_mb):
     """Poisson arrivals of jobs (2,000-2,000,000 sites, 10^4-10^7 trials) at
     `load` times the given capacity (load 0: every job arrives at once, which
     measures the capacity itself); latency = completion - arrival."""
-    jobs = wl.config5_jobs(n_jobs=n_jobs)
+    jobs = wl.served_jobs(n_jobs=n_jobs)
     T = np.array([j.n_trials for j in jobs], dtype=np.float64)
     if load > 0:
         rate = load * capacity_trials_per_s / T.mean()
@@ -349,7 +349,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     # ---- inputs, resident in HBM -------------------------------------------------
-    p = wl.config2()
+    p = wl.fcc20_chain()
     N, M, S = p.N, p.M, p.S
     K = args.eval_configs
     eval_in = torch.from_numpy(wl.iid_configs(N, M, min(K, 2048), seed=2)).cuda()
@@ -368,16 +368,16 @@ def main():
     log = torch.zeros((p.n_trials, 4), dtype=torch.int32, device="cuda")
     par = pb.make_params(p.seed, p.chain_id, p.n_trials, p.B)
 
-    p1 = wl.config1()
+    p1 = wl.fcc4_chain()
     chain1_0 = torch.from_numpy(p1.species).cuda()
     chain1 = chain1_0.clone()
     par1 = pb.make_params(p1.seed, p1.chain_id, p1.n_trials, p1.B)
-    p3c = wl.config3()
+    p3c = wl.fcc40_chain()
     chain3_0 = torch.from_numpy(p3c.species).cuda()
     chain3 = chain3_0.clone()
     par3 = pb.make_params(p3c.seed, p3c.chain_id, p3c.n_trials, p3c.B)
 
-    chains = wl.config4(n_chains=args.chains)
+    chains = wl.mixed_chains(n_chains=args.chains)
     bspecies0 = torch.from_numpy(np.concatenate([c.species for c in chains])).cuda()
     bspecies = bspecies0.clone()
     boff = np.concatenate([[0], np.cumsum([c.N for c in chains])])
@@ -390,7 +390,7 @@ def main():
     pack_ms = 1e3 * (time.perf_counter() - t_pack)
     b_trials = sum(c.n_trials for c in chains)
 
-    p3 = wl.config3()
+    p3 = wl.fcc40_chain()
     K3 = 4096
     eval3_in = None
     if "eval3" in legs:
@@ -620,7 +620,7 @@ def main():
         # FCC 20^3 with target 0 starts near its optimum; FCC 40^3 with a nonzero
         # target is far from it (its DISJOINT chain meets the target within ~10^5 trials)
         out["best_vs_disjoint"] = {"fcc20": best_vs_disjoint(pb, p, torch),
-                                   "fcc40": best_vs_disjoint(pb, wl.config3(), torch, T=200_000)}
+                                   "fcc40": best_vs_disjoint(pb, wl.fcc40_chain(), torch, T=200_000)}
     if not args.no_global:
         progress("global search")
         out["global_search"] = global_search(pb, p, torch)

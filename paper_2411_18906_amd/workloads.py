@@ -92,7 +92,7 @@ def cells_for(lattice: int, n_target: float) -> int:
 # The five workloads: shapes, compositions and budgets.
 # --------------------------------------------------------------------------
 
-def config1(seed: int = 1, chain_id: int = 0) -> Problem:
+def fcc4_chain(seed: int = 1, chain_id: int = 0) -> Problem:
     """FCC 4x4x4 (256 sites), 4 equiatomic species, shells 1-2, alpha target 0,
     unit weights, 10^4 trials, B = 64 (the paper's 64-task preset)."""
     L = (4, 4, 4)
@@ -100,7 +100,7 @@ def config1(seed: int = 1, chain_id: int = 0) -> Problem:
     return Problem(FCC, L, 4, 2, np.zeros((2, 4, 4)), np.ones(2), sp, seed, chain_id, 10**4, 64)
 
 
-def config2(seed: int = 1, chain_id: int = 0) -> Problem:
+def fcc20_chain(seed: int = 1, chain_id: int = 0) -> Problem:
     """FCC 20x20x20 (32,000 sites), 5 equiatomic species, shells 1-3, target 0,
     unit weights, 10^6 trials."""
     L = (20, 20, 20)
@@ -108,7 +108,7 @@ def config2(seed: int = 1, chain_id: int = 0) -> Problem:
     return Problem(FCC, L, 5, 3, np.zeros((3, 5, 5)), np.ones(3), sp, seed, chain_id, 10**6, 64)
 
 
-def config3(seed: int = 1, chain_id: int = 0) -> Problem:
+def fcc40_chain(seed: int = 1, chain_id: int = 0) -> Problem:
     """FCC 40x40x40 (256,000 sites), 4 species at 0.25, shells 1-2, projected
     random target in [-0.2, 0.2], weights (1.0, 0.5), 10^7 trials."""
     L = (40, 40, 40)
@@ -141,7 +141,7 @@ def random_chain(rng: np.random.Generator, seed: int, chain_id: int, n_lo: float
     return Problem(lattice, (Lc, Lc, Lc), M, S, tgt, w, sp, seed, chain_id, n_trials, B)
 
 
-def config4(n_chains: int = 512, seed: int = 4, n_trials: int = 10**5) -> list:
+def mixed_chains(n_chains: int = 512, seed: int = 4, n_trials: int = 10**5) -> list:
     """Batched: FCC/BCC at 50/50, 250-16,000 sites log-uniform, 3-6 species at
     5-35 % (Dirichlet, rounded by largest remainder), projected targets, shell
     weights (1.0, 0.5), 10^5 trials per chain."""
@@ -149,7 +149,7 @@ def config4(n_chains: int = 512, seed: int = 4, n_trials: int = 10**5) -> list:
     return [random_chain(rng, seed, i, 250, 16000, n_trials) for i in range(n_chains)]
 
 
-def config5_jobs(n_jobs: int = 2000, seed: int = 5, n_lo: float = 2e3, n_hi: float = 2e6,
+def served_jobs(n_jobs: int = 2000, seed: int = 5, n_lo: float = 2e3, n_hi: float = 2e6,
                  t_lo: float = 1e4, t_hi: float = 1e7) -> list:
     """Serving: job sizes 2,000-2,000,000 sites log-uniform, FCC/BCC, 3-6
     species, trial budgets log-uniform in [10^4, 10^7].  The job id is the

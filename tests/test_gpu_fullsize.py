@@ -41,9 +41,9 @@ def served_sample(jobs):
 @pytest.fixture(scope="module")
 def refs():
     """Oracle results of every case of this module, computed in the pool."""
-    c2, c3 = wl.config2(), wl.config3()
-    chains = wl.config4(n_chains=512)
-    jobs = wl.config5_jobs(n_jobs=200)
+    c2, c3 = wl.fcc20_chain(), wl.fcc40_chain()
+    chains = wl.mixed_chains(n_chains=512)
+    jobs = wl.served_jobs(n_jobs=200)
     sample = served_sample(jobs)
     fut = {
         "c3": op.submit_chain(op.chain_job(c3)),                  # the longest: first
@@ -84,9 +84,9 @@ def test_fcc20_chain_full_length(refs):
 @pytest.mark.parametrize("which", ["fcc20", "fcc40"])
 def test_full_eval_batch_sampled(refs, which):
     if which == "fcc20":
-        p, K, blk = wl.config2(), 32768, 2048
+        p, K, blk = wl.fcc20_chain(), 32768, 2048
     else:
-        p, K, blk = wl.config3(), 4096, 256
+        p, K, blk = wl.fcc40_chain(), 4096, 256
     base = torch.from_numpy(wl.iid_configs(p.N, p.M, blk, seed=2 if which == "fcc20" else 4)).cuda()
     g = torch.Generator(device="cuda").manual_seed(3 if which == "fcc20" else 5)
     batch = torch.cat([base] + [base[:, torch.randperm(p.N, device="cuda", generator=g)]

@@ -77,7 +77,7 @@ def test_global_search_rejects_bad_parameters():
 
 def test_global_search_fcc20_performance_preset_properties():
     # the paper's Performance-Optimized preset on the FCC 20^3 5-species problem
-    p = wl.config2()
+    p = wl.fcc20_chain()
     comp = np.bincount(p.species, minlength=p.M)
     best = torch.full((p.N,), -1, dtype=torch.int8, device="cuda")
     st, hist = pb.pyhea_global_search(p.lattice, p.L, p.M, p.S, p.target, p.weight, comp, best,

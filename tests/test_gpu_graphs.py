@@ -35,7 +35,7 @@ def _check(chains, seeds, T, fin, offsets, stats, which):
 
 
 def test_batch_replays_equal_oracle_with_new_seeds():
-    chains = wl.config4(n_chains=12, seed=31, n_trials=1500)
+    chains = wl.mixed_chains(n_chains=12, seed=31, n_trials=1500)
     scratch = torch.zeros(1 << 20, device="cuda")
     flags = []
     for call in range(5):
@@ -51,7 +51,7 @@ def test_batch_replays_equal_oracle_with_new_seeds():
 
 
 def test_graphs_off_runs_eagerly_and_equal():
-    chains = wl.config4(n_chains=6, seed=32, n_trials=1200)
+    chains = wl.mixed_chains(n_chains=6, seed=32, n_trials=1200)
     seeds = [7 + i for i in range(len(chains))]
     pb.pyhea_tune_graphs(False)
     try:
@@ -70,7 +70,7 @@ def test_graphs_off_runs_eagerly_and_equal():
 
 
 def test_single_chain_replays_and_logs():
-    p = wl.config1(seed=9)
+    p = wl.fcc4_chain(seed=9)
     logs = []
     for call in range(4):
         d = torch.from_numpy(p.species).cuda()
@@ -92,7 +92,7 @@ def test_single_chain_replays_and_logs():
 def test_many_structures_evict_and_stay_correct():
     """More structures than are kept: each is seen twice in turn (recorded, then
     dropped as others come), and the first one is right again at the end."""
-    sets = [wl.config4(n_chains=3 + k, seed=40 + k, n_trials=800) for k in range(6)]
+    sets = [wl.mixed_chains(n_chains=3 + k, seed=40 + k, n_trials=800) for k in range(6)]
     for rep in range(2):
         for k, chains in enumerate(sets):
             seeds = [rep * 100 + k * 10 + i for i in range(len(chains))]
@@ -110,7 +110,7 @@ def test_many_structures_record_and_replay():
     the later ones replay its recording (or, past the 32 recorded structures a
     process keeps, run eagerly too), and every call equals the oracle."""
     for k in range(10):
-        chains = wl.config4(n_chains=2 + k, seed=60 + k, n_trials=600)
+        chains = wl.mixed_chains(n_chains=2 + k, seed=60 + k, n_trials=600)
         seeds = [k * 10 + i for i in range(len(chains))]
         flags = []
         for _ in range(3):

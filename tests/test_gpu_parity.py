@@ -336,8 +336,8 @@ def assert_same_chain(o, g):
 
 MC_CASES = [
     # lattice, L, M, S, B, mode, T
-    (orc.FCC, (4, 4, 4), 4, 2, 64, 0, 10_000),     # config-1 shape, DISJOINT
-    (orc.FCC, (4, 4, 4), 4, 2, 64, 1, 10_000),     # config-1 shape, BEST
+    (orc.FCC, (4, 4, 4), 4, 2, 64, 0, 10_000),     # FCC 4^3 shape, DISJOINT
+    (orc.FCC, (4, 4, 4), 4, 2, 64, 1, 10_000),     # FCC 4^3 shape, BEST
     (orc.FCC, (5, 4, 3), 5, 3, 100, 0, 5_000),     # B not a multiple of 64, ragged last step
     (orc.BCC, (5, 5, 5), 6, 4, 256, 0, 6_000),     # BCC shell 4 (halo 2), 4 slot groups
     (orc.BCC, (4, 4, 4), 3, 2, 1, 1, 800),         # B = 1 BEST: Algorithm 2
@@ -358,8 +358,8 @@ def test_mc_run_matches_oracle(case):
     assert_same_chain(o, g)
 
 
-def test_mc_run_config1_exact():
-    p = wl.config1()
+def test_mc_run_fcc4_chain_exact():
+    p = wl.fcc4_chain()
     o, g = run_both(p.lattice, p.L, p.M, p.S, p.species, p.target, p.weight, seed=p.seed,
                     chain=p.chain_id, T=p.n_trials, B=p.B)
     assert_same_chain(o, g)
@@ -447,7 +447,7 @@ def test_asymmetric_target_matches_oracle(shape, variant):
 
 
 def test_mc_batch_equals_each_chain_alone():
-    chains = wl.config4(n_chains=24, seed=11, n_trials=3000)
+    chains = wl.mixed_chains(n_chains=24, seed=11, n_trials=3000)
     species = np.concatenate([c.species for c in chains])
     offsets = np.concatenate([[0], np.cumsum([c.N for c in chains])])
     d = dev(species)
@@ -470,7 +470,7 @@ def test_mc_batch_equals_each_chain_alone():
 
 @pytest.mark.parametrize("defect", ["out_of_range", "absent_species"])
 def test_mc_batch_rejects_bad_chain(defect):
-    chains = wl.config4(n_chains=6, seed=12, n_trials=500)
+    chains = wl.mixed_chains(n_chains=6, seed=12, n_trials=500)
     species = np.concatenate([c.species for c in chains])
     offsets = np.concatenate([[0], np.cumsum([c.N for c in chains])])
     bad = species.copy()
@@ -497,7 +497,7 @@ def test_mc_batch_rejects_bad_chain(defect):
 
 
 def test_mc_run_rejects_bad_species_and_leaves_it_unchanged():
-    c = wl.config4(n_chains=1, seed=13, n_trials=400)[0]
+    c = wl.mixed_chains(n_chains=1, seed=13, n_trials=400)[0]
     bad = c.species.copy()
     bad[5] = -3
     d = dev(bad)
@@ -553,7 +553,7 @@ def test_threshold_acceptance_matches_oracle(case, K, variant):
 
 def test_threshold_acceptance_in_a_batch():
     """Chains with and without a threshold side by side in one batched call."""
-    chains = wl.config4(n_chains=12, seed=13, n_trials=2000)
+    chains = wl.mixed_chains(n_chains=12, seed=13, n_trials=2000)
     species = np.concatenate([c.species for c in chains])
     offsets = np.concatenate([[0], np.cumsum([c.N for c in chains])])
     taus = [threshold_for(c.lattice, c.L, c.M, c.S, c.species, c.target, c.weight) if i % 2 else 0.0

@@ -75,7 +75,7 @@ def test_budget_forces_queueing_and_is_never_exceeded():
 
 
 def test_errors_cancel_and_unknown_ids():
-    p = wl.config1()
+    p = wl.fcc4_chain()
     with pb.Server(hbm_budget_bytes=128 << 10, max_slots=2, steps_per_round=8) as srv:
         bad = p.species.copy()
         bad[0] = 9
@@ -84,7 +84,7 @@ def test_errors_cancel_and_unknown_ids():
                                    pb.make_params(1, 0, 100))
         assert e.value.code == pb.EINVAL
         with pytest.raises(pb.PyheaError):        # too big for the budget
-            big = wl.config3()
+            big = wl.fcc40_chain()
             srv.pyhea_serve_submit(2, big.lattice, big.L, big.M, big.S, big.target, big.weight,
                                    big.species, pb.make_params(1, 0, 100))
         srv.pyhea_serve_submit(3, p.lattice, p.L, p.M, p.S, p.target, p.weight, p.species,

@@ -32,7 +32,7 @@ def chain_stats(p, T, measure=True):
 
 
 def test_measured_shape_is_reported_and_results_unchanged():
-    p = wl.config1()
+    p = wl.fcc4_chain()
     st, sp = chain_stats(p, 3000)
     assert st["shape_measured"] == 1 and st["shape"] > 0
     sp_o, _, st_o, _ = orc.mc_run(p.lattice, p.L, p.M, p.S, p.target, p.weight, p.species, seed=p.seed,
@@ -45,7 +45,7 @@ def test_measured_shape_is_reported_and_results_unchanged():
 
 def test_batch_reports_model_shapes():
     """Batches keep the cost model's shapes (reported, not measured)."""
-    chains = wl.config4(n_chains=8, seed=21, n_trials=2000)
+    chains = wl.mixed_chains(n_chains=8, seed=21, n_trials=2000)
     species = np.concatenate([c.species for c in chains])
     offsets = np.concatenate([[0], np.cumsum([c.N for c in chains])])
     d = torch.from_numpy(species).cuda()
@@ -66,7 +66,7 @@ CHILD = textwrap.dedent("""
     import torch
     from paper_2411_18906_amd import binding as pb
     from paper_2411_18906_amd import workloads as wl
-    p = wl.config1(seed=3)
+    p = wl.fcc4_chain(seed=3)
     d = torch.from_numpy(p.species).cuda()
     st, _ = pb.pyhea_mc_run(p.lattice, p.L, p.M, p.S, p.target, p.weight, d,
                             pb.make_params(p.seed, 0, 2000, p.B), None)

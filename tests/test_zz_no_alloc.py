@@ -31,7 +31,7 @@ def run(fn, p, batch):
 @pytest.mark.parametrize("case", ["fcc20_split", "fcc8_whole", "bcc_gather"])
 def test_noalloc_equals_allocating_entry_point_two_calls(case):
     if case == "fcc20_split":
-        p, sizes = wl.config2(), (6, 3)          # few configurations: each spread over many workgroups
+        p, sizes = wl.fcc20_chain(), (6, 3)          # few configurations: each spread over many workgroups
     elif case == "fcc8_whole":
         p, sizes = problem(wl.FCC, (8, 8, 8), 4, 2, 21), (700, 65)
     else:
