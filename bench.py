@@ -34,6 +34,18 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# The serving leg spreads each round's launch shapes over 16 streams.  The HIP
+# runtime serves a process's streams from GPU_MAX_HW_QUEUES hardware queues (4
+# by default) and launches that share a queue run one after another, so this
+# process asks for at least 16.  The runtime reads it once, when it starts (the
+# first torch or library call), so it is set here.
+try:
+    _queues = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+except ValueError:
+    _queues = 4
+if _queues < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
+
 HBM_PEAK_GBPS = 8000.0
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes per clock x clock
 METRIC = "MC trial swaps/sec + full-SRO eval GB/s; batched vs plain at equal SRO error"
@@ -271,6 +283,7 @@ def serve(pb, wl, n_jobs, capacity_trials_per_s, load, budget_mb):
             "latency_ms_max": float(lat.max()), "admission_wait_ms_p50": float(np.percentile(wait, 50)),
             "admission_wait_ms_p99": float(np.percentile(wait, 99)), "trials": int(trials), "span_s": span,
             "trials_per_s": trials / span, "rounds": c["rounds"], "sites_total": int(sum(j.N for j in jobs)),
+            "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
             "p99_tail_jobs": tail}
 
 

@@ -295,11 +295,17 @@ pyhea_status pyhea_mc_batch(int32_t n_chains, const pyhea_lattice *lats,
  * (pyhea_mc_run semantics, chain_id = job id); a worker thread admits queued
  * jobs while free slots and the HBM budget allow, keeps their configurations
  * and count tables resident on the device, advances all resident jobs in
- * rounds of one persistent launch, and retires finished jobs as they end, so
+ * rounds of one persistent launch per launch shape (the shapes on up to 16
+ * streams, which overlap as far as the HIP runtime's hardware queues allow:
+ * GPU_MAX_HW_QUEUES, 4 by default), and retires finished jobs as they end, so
  * jobs that arrive while others run join the next round.
  *   hbm_budget_bytes  device bytes the resident jobs may hold in total.
  *   max_slots         jobs resident at once.
- *   steps_per_round   MC steps per job per round (0 = library default).
+ *   steps_per_round   MC steps per round of the launch shape whose chains take
+ *                     longest per step (0 = library default, 256); the other
+ *                     shapes run as many steps as their measured time per step
+ *                     fits in the same time, at most 16 times as many.  A
+ *                     job's result does not depend on where rounds cut it.
  */
 pyhea_status pyhea_serve_open(int64_t hbm_budget_bytes, int32_t max_slots,
                               int32_t steps_per_round, void **server);

@@ -5,8 +5,12 @@
 // memory released), (2) admits queued jobs in arrival order while a slot is
 // free and their HBM footprint fits the budget (configuration, padded copy,
 // counts and tables stay resident on the device), and (3) advances every
-// resident job by up to `steps_per_round` MC steps with one persistent launch
-// per launch shape, the shapes on separate streams so they overlap.  A job's
+// resident job with one persistent launch per launch shape, the shapes on
+// separate streams so they overlap.  The launch whose chains take longest per
+// step runs `steps_per_round` steps; every other launch runs as many more
+// steps (up to kMaxStepScale times as many) as its chains' measured time per
+// step allows in the same time, so that a round's launches end together
+// instead of the fast ones idling until the slowest ends.  A job's
 // trajectory depends only on its own inputs (seed, chain id = job id, B,
 // budget): rounds are cut at step boundaries and the chain state (step, trial
 // and depth counters, counts, configuration) persists between launches.
@@ -14,6 +18,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <climits>
 #include <condition_variable>
 #include <cstring>
@@ -103,6 +108,17 @@ struct Job {
 
 int64_t job_footprint(const Geometry &g, int store) { return (int64_t)job_layout(g, store).total; }
 
+// Streams a round's launches are spread over.  The HIP runtime serves a
+// process's streams from a fixed number of hardware queues (GPU_MAX_HW_QUEUES,
+// 4 unless the environment sets more) and launches that share a queue run one
+// after another, so the launches overlap as far as the queues allow.
+constexpr int kServeStreams = 16;
+// A launch runs at most this many times the round's base step count.
+constexpr int kMaxStepScale = 16;
+
+// The launch shape of a group of resident jobs (one persistent launch each round).
+using GroupKey = std::tuple<int, int, int, int, int, int, int, int>;
+
 struct Server {
     int device = 0;
     int64_t budget = 0;
@@ -119,6 +135,10 @@ struct Server {
     int64_t n_submitted = 0, n_admitted = 0, n_finished = 0, n_rejected = 0, n_rounds = 0;
     int64_t bytes_resident = 0;
     std::vector<hipStream_t> streams;
+    // milliseconds per MC step of each launch shape's last launches (a running
+    // mean), and the events that time each launch of a round
+    std::map<GroupKey, double> ms_per_step;
+    std::vector<hipEvent_t> events;
     // device tables sized for max_slots: the round's descriptors, their gathered
     // states, and (for admission and retirement) descriptors and count tasks
     void *desc_dev = nullptr, *state_dev = nullptr, *aux_desc_dev = nullptr, *task_dev = nullptr;
@@ -364,19 +384,45 @@ void Server::run() {
             continue;
         }
         // one round: group by launch shape, one stream per group
-        std::map<std::tuple<int, int, int, int, int, int, int, int>, std::vector<Job *>> groups;
+        std::map<GroupKey, std::vector<Job *>> groups;
         for (Job *j : run_set)
             groups[{j->store, j->g.M, j->g.S, j->params.cand_per_step, j->W, j->bal, j->K, j->CH}].push_back(j);
         std::vector<ChainDesc> descs;
         std::vector<Job *> order;
         std::vector<std::pair<size_t, std::vector<Job *>>> launches;
+        std::vector<GroupKey> keys;
         for (auto &kv : groups) {
+            keys.push_back(kv.first);
             launches.push_back({descs.size(), kv.second});
             for (Job *j : kv.second) {
                 descs.push_back(j->desc);
                 order.push_back(j);
             }
         }
+        // steps per launch: the slowest measured shape runs the base count, the
+        // others as many steps as fit in the time it takes (shapes not yet
+        // measured run the base count)
+        std::vector<int> steps(launches.size(), steps_per_round);
+        {
+            double t_round = 0.0;
+            for (const GroupKey &k : keys) {
+                auto it = ms_per_step.find(k);
+                if (it != ms_per_step.end()) t_round = std::max(t_round, it->second * steps_per_round);
+            }
+            for (size_t gi = 0; gi < launches.size(); ++gi) {
+                auto it = ms_per_step.find(keys[gi]);
+                if (it == ms_per_step.end() || !(it->second > 0.0)) continue;
+                const double n = std::floor(t_round / it->second);
+                const double cap = std::min<double>((double)steps_per_round * kMaxStepScale, (double)(INT_MAX / 2));
+                steps[gi] = (int)std::min<double>(cap, std::max<double>((double)steps_per_round, n));
+            }
+        }
+        while (events.size() < 2 * launches.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) break;
+            events.push_back(e);
+        }
+        const bool timed = events.size() >= 2 * launches.size();
         bool ok = hipMemcpyAsync(desc_dev, descs.data(), descs.size() * sizeof(ChainDesc), hipMemcpyHostToDevice,
                                  s0) == hipSuccess;
         hipEvent_t ready = nullptr;
@@ -389,10 +435,11 @@ void Server::run() {
             for (Job *j : L.second) lds = std::max(lds, j->lds);
             hipStream_t s = streams[gi % streams.size()];
             ok = s == s0 || hipStreamWaitEvent(s, ready, 0) == hipSuccess;
+            if (timed) ok = ok && hipEventRecord(events[2 * gi], s) == hipSuccess;
             ok = ok && launch_mc((const ChainDesc *)desc_dev + L.first, (int)L.second.size(), j0->store, j0->g.M,
                                  j0->g.S, j0->params.cand_per_step, j0->W, j0->bal, j0->K, j0->CH, lds,
-                                 steps_per_round,
-                                 s) == hipSuccess;
+                                 steps[gi], s) == hipSuccess;
+            if (timed) ok = ok && hipEventRecord(events[2 * gi + 1], s) == hipSuccess;
         }
         for (size_t i = 0; i < streams.size(); ++i) ok = ok && hipStreamSynchronize(streams[i]) == hipSuccess;
         if (ready) (void)hipEventDestroy(ready);
@@ -403,6 +450,23 @@ void Server::run() {
         ok = ok && hipMemcpyAsync(states.data(), state_dev, order.size() * sizeof(ChainState), hipMemcpyDeviceToHost,
                                   s0) == hipSuccess;
         ok = ok && hipStreamSynchronize(s0) == hipSuccess;
+        // time per step of each shape, from launches in which no chain ended early
+        if (ok && timed) {
+            size_t at = 0;
+            for (size_t gi = 0; gi < launches.size(); ++gi) {
+                bool ended = false;
+                for (size_t i = 0; i < launches[gi].second.size(); ++i) ended = ended || states[at + i].done;
+                at += launches[gi].second.size();
+                float ms = 0.0f;
+                if (ended || hipEventElapsedTime(&ms, events[2 * gi], events[2 * gi + 1]) != hipSuccess) continue;
+                const double v = (double)ms / steps[gi];
+                auto it = ms_per_step.find(keys[gi]);
+                if (it == ms_per_step.end())
+                    ms_per_step[keys[gi]] = v;
+                else
+                    it->second = 0.5 * (it->second + v);
+            }
+        }
         std::vector<Job *> finished, cancelled;
         {
             std::lock_guard<std::mutex> lk(mu);
@@ -466,7 +530,7 @@ pyhea_status pyhea_serve_open(int64_t hbm_budget_bytes, int32_t max_slots, int32
     s->max_slots = max_slots;
     s->steps_per_round = steps_per_round > 0 ? steps_per_round : 256;
     s->lds_budget = max_lds_per_block();
-    s->streams.resize(4);  // [0]: admission, retirement and read-back; all four: the rounds' launches
+    s->streams.resize(kServeStreams);  // [0]: admission, retirement and read-back; all: the rounds' launches
     for (auto &st : s->streams) {
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
             delete s;
@@ -539,7 +603,13 @@ pyhea_status pyhea_serve_submit(void *server, uint64_t job_id, const pyhea_latti
     const int E = g.S * g.M * g.M;
     j->target.assign(obj->target, obj->target + E);
     j->weight.assign(obj->weight, obj->weight + g.S);
+    // shapes for a full server (max_slots chains resident) keep small chains'
+    // workgroups narrow so that many share a CU; a job whose configuration
+    // lives in HBM takes the shape of a chain with a CU to itself (more steps
+    // per pass): such jobs are few under any HBM budget, and their time per step
+    // sets the pace of a round
     LaunchShape ls = choose_launch(g, params->cand_per_step, s->lds_budget, 0, s->max_slots);
+    if (ls.store == kStoreGlobal) ls = choose_launch(g, params->cand_per_step, s->lds_budget, 0, 256);
     // a shape measured earlier for this kind of chain (the server itself never probes)
     LaunchShape t;
     if (measure_enabled() && tuned_launch(tune_key(g, params->cand_per_step, s->max_slots), &t)) {
@@ -692,6 +762,7 @@ pyhea_status pyhea_serve_close(void *server) {
     (void)hipStreamSynchronize(s->streams[0]);
     for (void *p : {s->desc_dev, s->state_dev, s->aux_desc_dev, s->task_dev})
         if (p) (void)hipFree(p);
+    for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
     for (auto st : s->streams) (void)hipStreamDestroy(st);
     delete s;
     return PYHEA_OK;

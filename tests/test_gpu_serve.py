@@ -130,3 +130,30 @@ def test_jobs_submitted_while_others_run_join_later_rounds():
     for p in late:
         sp_a, _ = alone(p, p.n_trials)
         np.testing.assert_array_equal(res[p.chain_id][1], sp_a)
+
+
+@pytest.mark.parametrize("base_steps", [3, 50])
+def test_launch_shapes_take_their_own_step_counts_and_stay_exact(base_steps):
+    # small jobs held in LDS beside large HBM-resident ones: the faster shapes
+    # run more steps per round (sized from their measured step times), so rounds
+    # cut every job at other places than a fixed count would; each result must
+    # still be the job's result alone
+    rng = np.random.Generator(np.random.Philox(77))
+    jobs = []
+    for i in range(8):
+        hi = 3000 if i % 2 else 300000
+        jobs.append(wl.random_chain(rng, 77, 300 + i, 2000, hi, int(rng.integers(3000, 20000))))
+    with pb.Server(hbm_budget_bytes=256 << 20, max_slots=8, steps_per_round=base_steps) as srv:
+        for p in jobs:
+            srv.pyhea_serve_submit(p.chain_id, p.lattice, p.L, p.M, p.S, p.target, p.weight,
+                                   p.species, pb.make_params(p.seed, 0, p.n_trials, p.B))
+        results = {p.chain_id: srv.pyhea_serve_poll(p.chain_id, p.N) for p in jobs}
+        c = srv.pyhea_serve_counters()
+    assert c["finished"] == len(jobs) and c["rounds"] > 1
+    for p in jobs:
+        code, sp, st, _ = results[p.chain_id]
+        assert code == pb.OK
+        sp_a, st_a = alone(p, p.n_trials)
+        np.testing.assert_array_equal(sp, sp_a)
+        for f in ["trials", "null_trials", "commits", "steps", "S", "F"]:
+            assert st[f] == st_a[f], f
