@@ -578,6 +578,15 @@ def main():
     if "lat" in legs:
         ms = np.array(leg_ms("lat0", "lat1"))
         out["sro_eval_one_config_us"] = float(ms.mean() * 1e3 / lat_reps)
+        # the single-configuration entry point itself, synchronous: counts, alpha,
+        # S and F of the FCC 20^3 configuration read back to the host per call
+        one = chain0.contiguous()
+        for _ in range(5):
+            pb.pyhea_sro_eval(p.lattice, p.L, M, S, one, p.target, p.weight)
+        t_s = time.perf_counter()
+        for _ in range(50):
+            pb.pyhea_sro_eval(p.lattice, p.L, M, S, one, p.target, p.weight)
+        out["sro_eval_sync_us"] = (time.perf_counter() - t_s) / 50 * 1e6
     if "batch" in legs:
         ms = np.array(leg_ms("batch0", "batch1"))
         bst = evs[-1]["batch_stats"]

@@ -689,29 +689,8 @@ __device__ __forceinline__ void add_slots(const int32_t *slots, const BitDesc &b
     }
 }
 
-// slot sums -> full counts N[k][i][j] (one thread per configuration)
-template <int M, int S>
-__global__ void finalize_bits_kernel(BitDesc bd, int64_t K, const int32_t *__restrict__ partial,
-                                     int32_t *__restrict__ counts, int32_t *__restrict__ bad) {
-    constexpr int P = Pairs<M>::P;
-    constexpr int NP = Pairs<M>::NP;
-    const int64_t kc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (kc >= K) return;
-    int32_t pa[S * NP + P + 1];
-    add_slots<M, S>(partial + kc * bd.nchunks * (int64_t)bd.partial_stride, bd, 0, 1, pa);
-    int32_t *c = counts + kc * (int64_t)(S * M * M);
-    int64_t n[M];
-    int64_t rest = bd.N;
-    for (int i = 0; i < P; ++i) {
-        n[i] = pa[S * NP + i];
-        rest -= n[i];
-    }
-    n[M - 1] = rest;
-    bad[kc] = pa[S * NP + P] ? 1 : 0;
-    for (int k = 0; k < S; ++k) expand_shell<M>(pa + k * NP, bd.zk[k], n, c + k * M * M);
-}
-
-// slot sums -> counts and Eq. 2-3 (one 64-thread block per configuration)
+// slot sums -> counts, and Eq. 2-3 when S_F is given (one 64-thread block per
+// configuration: the slot sums, the entries and the rows are spread over its lanes)
 template <int M, int S>
 __global__ void __launch_bounds__(64) finalize_objective_kernel(BitDesc bd, const int32_t *__restrict__ partial,
                                                                int32_t *__restrict__ counts,
@@ -725,7 +704,8 @@ __global__ void __launch_bounds__(64) finalize_objective_kernel(BitDesc bd, cons
     const int64_t kc = blockIdx.x;
     add_slots<M, S>(partial + kc * bd.nchunks * (int64_t)bd.partial_stride, bd, threadIdx.x, blockDim.x, lsum);
     __syncthreads();
-    epilogue<M, S>(lsum, bd, lc, lsq, lrow, counts + kc * (int64_t)(S * M * M), bad + kc, tw, S_F + 2 * kc);
+    epilogue<M, S>(lsum, bd, lc, lsq, lrow, counts + kc * (int64_t)(S * M * M), bad + kc, tw,
+                   S_F ? S_F + 2 * kc : nullptr);
 }
 
 
@@ -1119,12 +1099,9 @@ hipError_t launch_ms(const BitDesc &bd, int64_t K, const int8_t *species, int32_
                            species + k0 * (int64_t)bd.N, partial + k0 * bd.nchunks * bd.partial_stride,
                            counts + k0 * (int64_t)(S * M * M), bad + k0, tw, S_F ? S_F + 2 * k0 : nullptr);
     }
-    if (bd.nchunks > 1 && S_F)
+    if (bd.nchunks > 1)
         hipLaunchKernelGGL((finalize_objective_kernel<M, S>), dim3((unsigned)K), dim3(64), 0, stream, bd, partial,
                            counts, bad, tw, S_F);
-    else if (bd.nchunks > 1)
-        hipLaunchKernelGGL((finalize_bits_kernel<M, S>), dim3((unsigned)((K + 127) / 128)), dim3(128), 0, stream, bd, K,
-                           partial, counts, bad);
     return hipGetLastError();
 }
 

@@ -220,6 +220,67 @@ __global__ void objective_kernel(EvalDesc ed, int64_t K, const int32_t *__restri
     }
 }
 
+// objective_kernel for a few configurations: one 64-thread block per
+// configuration, its entries spread over the lanes and its rows summed by one
+// lane each, then the rows into Q_k and S by lane 0 -- the same expressions and
+// summation order as objective_kernel, so the results are the same bit for bit.
+__global__ void __launch_bounds__(64) objective_block_kernel(EvalDesc ed, const int32_t *__restrict__ counts,
+                                                             const int32_t *__restrict__ bad,
+                                                             const double *__restrict__ target,
+                                                             const double *__restrict__ weight,
+                                                             double *__restrict__ S_F, double *__restrict__ alpha) {
+    __shared__ int64_t n[kMaxSpecies];
+    __shared__ double lsq[kMaxShells * kMaxSpecies * kMaxSpecies];
+    __shared__ double lrow[kMaxShells * kMaxSpecies];
+    const int64_t kc = blockIdx.x;
+    const int tid = (int)threadIdx.x;
+    const int M = ed.M, E = ed.S * M * M;
+    const int32_t *c = counts + kc * E;
+    if (tid < M) {
+        int64_t r = 0;
+        for (int j = 0; j < M; ++j) r += c[tid * M + j];
+        n[tid] = r / ed.z0;
+    }
+    __syncthreads();
+    bool ok = bad[kc] == 0;
+    for (int i = 0; i < M; ++i) ok = ok && n[i] > 0;
+    if (!ok) {
+        if (target && tid == 0) {
+            S_F[2 * kc] = __longlong_as_double(0x7ff8000000000000ll);
+            S_F[2 * kc + 1] = __longlong_as_double(0x7ff8000000000000ll);
+        }
+        return;
+    }
+    for (int e = tid; e < E; e += blockDim.x) {
+        const int k = e / (M * M), i = (e / M) % M, j = e % M;
+        const double R = (double)ed.N / (double)(n[i] * n[j] * (int64_t)ed.zk[k]);
+        const double a = 1.0 - (double)c[e] * R;
+        if (alpha) alpha[kc * E + e] = a;
+        if (target) {
+            const double dd = a - target[e];
+            lsq[e] = dd * dd;
+        }
+    }
+    if (!target) return;
+    __syncthreads();
+    for (int r = tid; r < ed.S * M; r += blockDim.x) {
+        double row = 0.0;
+        for (int j = 0; j < M; ++j) row = row + lsq[r * M + j];
+        lrow[r] = row;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double sum = 0.0;
+        for (int k = 0; k < ed.S; ++k) {
+            double Q = 0.0;
+            for (int i = 0; i < M; ++i) Q = Q + lrow[k * M + i];
+            sum = sum + weight[k] * Q;
+        }
+        S_F[2 * kc] = sum;
+        S_F[2 * kc + 1] = sqrt(sum);
+    }
+}
+
 // Eq. 2-3 on a chain's maintained counts, binary64 in the host contract's order
 // (alpha = 1 - N R, (alpha - t)^2 summed along a row, rows into Q_k, S = sum_k
 // w_k Q_k), written to its state with F = sqrt(S).  One thread per chain.
@@ -387,6 +448,12 @@ hipError_t launch_count_tasks(const CountTask *tasks, const uint32_t *tile0, int
 hipError_t launch_objective_epilogue(const EvalDesc &ed, int64_t K, const int32_t *counts,
                                      const int32_t *bad, const double *target, const double *weight,
                                      double *S_F, double *alpha, hipStream_t stream) {
+    if (K <= 0) return hipSuccess;
+    if (K <= 1024) {   // few configurations: a block each rather than a lane each
+        hipLaunchKernelGGL(objective_block_kernel, dim3((unsigned)K), dim3(64), 0, stream, ed, counts, bad, target,
+                           weight, S_F, alpha);
+        return hipGetLastError();
+    }
     const int blocks = (int)((K + 255) / 256);
     hipLaunchKernelGGL(objective_kernel, dim3(blocks), dim3(256), 0, stream, ed, K, counts, bad, target,
                        weight, S_F, alpha);
