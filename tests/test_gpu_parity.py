@@ -571,3 +571,41 @@ def test_threshold_acceptance_in_a_batch():
         for f in ["trials", "null_trials", "commits", "steps"]:
             assert stats[i][f] == st_o[f], (i, f)
         assert stats[i]["S"] == st_o["S"]
+
+
+@pytest.mark.parametrize("K", [1023, 1025])
+def test_objective_lane_and_block_kernels_agree(K):
+    """alpha, S and F of the gather kernel's counts come from a block per
+    configuration for up to 1,024 configurations and from a lane per
+    configuration above: both give the oracle's values bit for bit, and the
+    first configurations' results do not depend on the batch size."""
+    lattice, L, M, S = orc.FCC, (3, 3, 2), 4, 2
+    N = orc.n_sites(lattice, L)
+    cfg = wl.iid_configs(N, M, K, seed=31)
+    cfg[3, :] = 0                      # species missing -> NaN
+    rng = np.random.default_rng(5)
+    tgt = rng.uniform(-0.2, 0.2, (S, M, M))
+    w = rng.uniform(0.1, 1.0, S)
+    pb.pyhea_tune_force_eval(0)
+    try:
+        counts = torch.zeros((K, S, M, M), dtype=torch.int32, device="cuda")
+        SF = torch.zeros((K, 2), dtype=torch.float64, device="cuda")
+        pb.pyhea_sro_eval_batch(lattice, L, M, S, dev(cfg), counts, tgt, w, SF)
+        few_c = torch.zeros((8, S, M, M), dtype=torch.int32, device="cuda")
+        few_SF = torch.zeros((8, 2), dtype=torch.float64, device="cuda")
+        pb.pyhea_sro_eval_batch(lattice, L, M, S, dev(cfg[:8].copy()), few_c, tgt, w, few_SF)
+        torch.cuda.synchronize()
+    finally:
+        pb.pyhea_tune_force_eval(-1)
+    sf = SF.cpu().numpy()
+    np.testing.assert_array_equal(few_c.cpu().numpy(), counts.cpu().numpy()[:8])
+    np.testing.assert_array_equal(few_SF.cpu().numpy(), sf[:8])   # NaN == NaN here
+    assert np.all(np.isnan(sf[3]))
+    c = counts.cpu().numpy()
+    for k in list(range(8)) + [K - 2, K - 1]:
+        if k == 3 or (np.bincount(cfg[k], minlength=M) == 0).any():
+            continue
+        want = orc.counts(lattice, L, M, S, cfg[k])
+        np.testing.assert_array_equal(c[k], want)
+        _, _, S_o, F_o = orc.alpha_objective(lattice, L, M, S, cfg[k], want, tgt, w)
+        assert sf[k, 0] == S_o and sf[k, 1] == F_o
